@@ -1,0 +1,195 @@
+"""Benchmark: stixel frames/s at 1024x440, stixel width 5, on one MI355X.
+
+One step = the whole hot path (column reduction, prefix tables, the
+three-class recurrence and backtracking) over one batch of 64 synthetic
+1024x440 frames (seeds 0..63), inputs resident in HBM.  The timed path is the
+persistent batched launch replayed from a HIP graph; the plain per-frame path
+(three kernels per frame, frames back to back on one stream) and per-frame /
+per-batch latency percentiles are reported beside it.
+
+Prints one JSON line.  Roofline of the dominant kernel (the persistent
+kernel): algorithmic work = 13 VALU lane-ops per (cut, row) pair of the
+recurrence, h(h+1)/2 pairs per column, against the plain VALU issue peak of
+256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s (the recurrence
+is min-plus, not a contraction, so MFMA peaks do not apply).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import glob
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "stixel frames/s @1024×440 w=5 (batched vs per-frame); p50/p99 frame latency"
+W, H, S_WIDTH, D_RANGE, FRAMES = 1024, 440, 5, 128, 64
+VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
+OPS_PER_PAIR = 13
+
+
+def pairs_per_frame(W=W, H=H, s=S_WIDTH):
+    return (W // s) * H * (H + 1) // 2
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1610_04124_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles():
+    """HBM bytes per launch of the persistent kernel from the committed PMC
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "batch_kernel_1024x440_b64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(frames, params, n_frames):
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    sample = frames[:n_frames]
+    oracle.frame(params, sample[0], nthreads=threads)            # load / warm
+    t0 = time.perf_counter()
+    for f in sample:
+        oracle.frame(params, f, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(sample) / dt, 3), "unit": "frames/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(sample)} of the {FRAMES} frames (seeds 0..{len(sample) - 1}), "
+                      f"C FP64 oracle, OpenMP over columns, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-frames", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--latency-frames", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(frames and columns are independent, see the design notes "
+                                   "on sharding)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    dev = torch.device("cuda", 0)
+    params = synth.make_params()
+    frames = [synth.generate_frame(synth.SceneSpec(seed=i)) for i in range(FRAMES)]
+    d_frames = [torch.from_numpy(f).to(dev) for f in frames]
+    h = P.Stixels(params)
+    outs = [h.new_output(W, H) for _ in range(FRAMES)]
+    stream = torch.cuda.Stream()            # a created stream: graphs cannot capture the null stream
+    torch.cuda.synchronize()
+
+    # ---------------- batched path: persistent launch replayed from a graph
+    batch = P.Batch(FRAMES, FRAMES * (W // S_WIDTH), H, D_RANGE)
+    items = list(zip([h] * FRAMES, d_frames, outs))
+    batch.capture(items, stream)
+    grid, ntasks = batch.info()
+    for _ in range(args.warmup):
+        batch.replay(stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        batch.replay(stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    batched_fps = FRAMES * args.steps / wall
+    ms_per_step = wall * 1e3 / args.steps
+    avg_launch_s = statistics.mean(launch_ms) * 1e-3
+
+    # ---------------- per-frame path: three kernels per frame, one stream
+    for i in range(FRAMES):
+        h.compute(d_frames[i], outs[i], stream)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for i in range(FRAMES):
+            h.compute(d_frames[i], outs[i], stream)
+    torch.cuda.synchronize()
+    per_frame_fps = FRAMES * reps / (time.perf_counter() - t0)
+    lat = []
+    for i in range(args.latency_frames):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        h.compute(d_frames[i % FRAMES], outs[i % FRAMES], stream)
+        b.record(stream)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+
+    # ---------------- roofline of the persistent kernel
+    ops = OPS_PER_PAIR * pairs_per_frame() * FRAMES
+    achieved = ops / avg_launch_s
+    traffic = traffic_from_profiles()
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK / 1e12, 4),
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
+                "kernel": "batch_kernel<7>", "ops_per_launch": ops,
+                "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
+
+    result = {
+        "metric": METRIC, "value": round(batched_fps, 2), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batch64_1024x440", "frames_per_step": FRAMES, "width": W,
+                   "height": H, "stixel_width": S_WIDTH, "max_disparity": D_RANGE,
+                   "columns_per_frame": W // S_WIDTH,
+                   "path": "persistent batched launch replayed from a HIP graph",
+                   "workgroups": grid, "tasks": ntasks},
+        "batched": {"fps": round(batched_fps, 2),
+                    "batch_latency_ms_p50": round(percentile(launch_ms, 0.5), 4),
+                    "batch_latency_ms_p99": round(percentile(launch_ms, 0.99), 4)},
+        "per_frame": {"fps": round(per_frame_fps, 2),
+                      "frame_latency_ms_p50": round(percentile(lat, 0.5), 4),
+                      "frame_latency_ms_p99": round(percentile(lat, 0.99), 4)},
+        "roofline": roofline,
+        "paper_context_fps": {"titan_x": 413, "tegra_x1": 26, "i7_980x_cpu": 13.3},
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(frames, params, args.cpu_frames)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

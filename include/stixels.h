@@ -1,0 +1,238 @@
+/*
+ * stixels.h -- C ABI of the gfx950 multi-stixel segmentation library.
+ *
+ * The library segments every column of a dense disparity map into ground,
+ * object and sky stixels (Hernandez-Juarez et al., "GPU-accelerated real-time
+ * stixel computation", Sec. 3): a W x h disparity map, a stixel width s and a
+ * camera whose ground slope and horizon are known go in (Sec. 3, Sec. 3.1);
+ * per reduced column, an ordered list of stixels {v_bottom, v_top, class}
+ * with an integer disparity for objects comes out (Sec. 3.3, Sec. 4.4).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named d_* are device (HIP) memory owned by the caller; host
+ *     pointers are named host_*.  The library never frees caller memory.
+ *   - Rows inside a column are bottom-up (v = 0 is the bottom image row,
+ *     Sec. 3.1); the input image itself is row-major, row 0 at the top.
+ *   - Classes: 0 = object, 1 = ground, 2 = sky.  Costs are negative log
+ *     likelihoods in nats.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Compute calls are asynchronous on that stream; results are valid once
+ *     the stream has been synchronised.
+ *   - Every call returns STIXELS_OK (0) or a negative STIXELS_E_* code; the
+ *     text of the last error of a handle is available from
+ *     stixels_last_error().  On error nothing is enqueued and no output is
+ *     touched.
+ */
+#ifndef STIXELS_H
+#define STIXELS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STIXELS_ABI_VERSION 1
+
+enum {
+    STIXELS_OK = 0,
+    STIXELS_E_INVALID_ARG = -1, /* null pointer, size out of the handle's limits, bad parameter */
+    STIXELS_E_RANGE = -2,       /* parameters would break exact arithmetic on the cost grid */
+    STIXELS_E_HIP = -3,         /* a HIP call or kernel launch failed */
+    STIXELS_E_NOMEM = -4        /* device or host allocation failed */
+};
+
+enum { STIXELS_OBJECT = 0, STIXELS_GROUND = 1, STIXELS_SKY = 2 };
+
+/* Stereo camera.  The ground slope in disparity per row is
+ * baseline * cos(pitch) / height and the ground disparity of top-down image
+ * row r is slope * (r - horizon_row) (Sec. 3.1, ground model).  horizon_row
+ * must be a multiple of 1/256 with |horizon_row| <= 2^20. */
+typedef struct {
+    double focal_px, baseline_m, cam_height_m, horizon_row, pitch_rad;
+} stixels_camera;
+
+/* Sensor model (Eq. 3-4) and prior model (Sec. 3, constraints 1-5).
+ * Class order of the arrays: object, ground, sky.  trans_cost[prev][cur] is
+ * the prior of a `cur` stixel directly above a `prev` stixel; INFINITY marks
+ * a forbidden pair.  Every prior value must be >= 0, first_cost must be
+ * finite and trans_cost[*][object] finite (an object can always follow). */
+typedef struct {
+    double p_out;                 /* outlier rate, 0 < p_out < 1 */
+    double sigma_disp;            /* disparity noise [px] */
+    double sigma_sky;             /* sky model sigma [px] */
+    double ground_slope_noise;    /* ground sigma = sqrt(sigma_disp^2 + (this * f_ground)^2) */
+    double object_depth_extent_m; /* object sigma = sqrt(sigma_disp^2 + (f^2 * this / (focal * baseline))^2) */
+    double bic_cost;              /* cost per stixel (constraint 1) */
+    double first_cost[3];         /* prior of the bottom stixel */
+    double trans_cost[3][3];      /* staggering (constraint 4) and pair costs */
+    double ordering_cost;         /* object over object with larger mean (constraint 3) */
+    double gravity_cost, gravity_tol_px; /* object over ground, mean below ground disparity (2) */
+    double diving_cost, diving_tol_px;   /* object over ground, mean above ground disparity (5) */
+    int32_t ordering_tol_px;      /* integer tolerance of the ordering constraint */
+    int32_t reserved0;
+} stixels_model;
+
+typedef struct {
+    stixels_camera camera;
+    stixels_model model;
+    int32_t stixel_width;        /* s: pixels reduced into one column, 1..16 */
+    int32_t max_disparity;       /* d_range: disparities 0..d_range-1, 2..256 */
+    int32_t max_width;           /* largest frame width accepted by stixels_compute */
+    int32_t max_height;          /* largest frame height, 1..1024 */
+    int32_t max_stixels_per_column; /* output records per column, 0 = the frame height */
+    int32_t reduce_mode;         /* 0 = lower median of the valid pixels, 1 = mean (Sec. 4.1) */
+    int32_t cost_grid_log2;      /* g: costs are multiples of 2^-g nats, 0..12 */
+    int32_t reserved0;
+} stixels_params;
+
+/* One stixel, 12 bytes.  v_bottom..v_top are inclusive bottom-up rows;
+ * disparity is the rounded mean of an object's valid pixels, 0 otherwise;
+ * cost is the stixel's data term plus its prior (Sec. 3.3), so the costs of
+ * a column sum to its total cost. */
+typedef struct {
+    int16_t v_bottom, v_top;
+    uint8_t cls, disparity;
+    uint16_t flags;              /* reserved, 0 */
+    float cost;
+} stixels_record;
+
+/* Caller-owned device output of one frame with ncols = floor(width / s)
+ * columns.  records holds `capacity` records per column; when a column has
+ * more stixels than that, its bottom-most `capacity` stixels are kept, counts
+ * is `capacity` and overflow is 1. */
+typedef struct {
+    int32_t *counts;             /* [ncols] */
+    stixels_record *records;     /* [ncols][capacity], bottom-up within a column */
+    float *total_cost;           /* [ncols], min(OB^{h-1}, GR^{h-1}, SK^{h-1}) */
+    uint8_t *overflow;           /* [ncols]; 1 = truncated to capacity, 255 = backtracking
+                                    found no predecessor (never expected; counts is 0) */
+    int32_t capacity;
+    int32_t reserved0;
+} stixels_output;
+
+typedef struct stixels_handle stixels_handle;
+
+/* Validate the parameters, build the offline cost tables of Sec. 3.4 on the
+ * host in FP64 (Eq. 4 for every pair of pixel disparity and model disparity,
+ * rounded to the 2^-g grid), upload them and allocate a workspace for frames
+ * up to max_width x max_height.  Must be called with the target device
+ * current.  Returns STIXELS_E_RANGE when (max_height + 1) * (largest table
+ * cost) plus the priors could leave the exact range of FP32 on the grid, or
+ * when max_height * max_disparity > 2^20. */
+int stixels_create(const stixels_params *params, stixels_handle **out);
+
+/* Release the tables and the workspace.  NULL is accepted. */
+int stixels_destroy(stixels_handle *h);
+
+/* Number of reduced columns of a frame of this width: floor(width / s). */
+int stixels_num_columns(const stixels_handle *h, int32_t width, int32_t *ncols);
+
+/* Records per column that an output for a frame of this height must hold. */
+int stixels_output_capacity(const stixels_handle *h, int32_t height, int32_t *capacity);
+
+/* Segment one frame (Sec. 4.1-4.4): column reduction and transpose, the
+ * per-column prefix-sum tables, the Eq. 5-6 recurrence and backtracking.
+ * d_disparity: device float32 [height][width], row-major, dense; a pixel is
+ * valid iff it is finite and >= 0.  width >= s, width <= max_width,
+ * 1 <= height <= max_height; out->capacity >= 1.  Uses the handle's
+ * workspace, so calls on one handle must not overlap (one handle per stream,
+ * or the batch API).  Allocates nothing. */
+int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, int32_t height,
+                    void *stream, const stixels_output *out);
+
+/* Text of the last error reported on this handle ("" if none); with NULL,
+ * the reason the last stixels_create or stixels_host_table of this thread
+ * failed. */
+const char *stixels_last_error(const stixels_handle *h);
+
+/* Static description of a status code. */
+const char *stixels_status_string(int code);
+
+/* ------------------------------------------------------------------ batch
+ * Many frames, possibly from different handles (cameras) and of different
+ * sizes, in one persistent launch: every (frame, column) pair is a task,
+ * tasks are ordered by decreasing h^2 (the cost of the recurrence, Sec. 3.3)
+ * and pulled by resident workgroups from a device counter.  Results are
+ * bitwise identical to stixels_compute on each frame alone. */
+typedef struct {
+    stixels_handle *handle;      /* camera model and tables; its workspace is not used */
+    const float *d_disparity;    /* device [height][width] */
+    int32_t width, height;
+    stixels_output out;
+} stixels_job;
+
+typedef struct {
+    int32_t max_jobs;            /* frames per call */
+    int32_t max_tasks;           /* (frame, column) pairs per call */
+    int32_t max_height;          /* tallest frame */
+    int32_t max_disparity;       /* largest d_range of the handles used */
+    int32_t workgroups;          /* persistent workgroups, 0 = chosen by the library */
+    int32_t reserved0;
+} stixels_batch_config;
+
+typedef struct stixels_batch stixels_batch;
+
+/* Allocate the task list, descriptors and per-workgroup scratch. */
+int stixels_batch_create(const stixels_batch_config *cfg, stixels_batch **out);
+int stixels_batch_destroy(stixels_batch *b);
+
+/* Enqueue one persistent launch over all jobs.  Jobs must fit the batch's
+ * limits and each job the limits of its handle.  Calls on one batch object
+ * must not overlap.  Host-side job descriptors are staged through pinned
+ * memory owned by the batch; nothing is allocated per call. */
+int stixels_batch_compute(stixels_batch *b, const stixels_job *jobs, int32_t n, void *stream);
+
+/* Capture the launch of stixels_batch_compute for these jobs into a HIP
+ * graph owned by the batch (replacing any previous one), then replay it with
+ * stixels_batch_replay.  The graph reads the same device buffers on every
+ * replay: refill the inputs in place between replays.  `stream` must be a
+ * created stream, not the null stream (which cannot be captured). */
+int stixels_batch_capture(stixels_batch *b, const stixels_job *jobs, int32_t n, void *stream);
+int stixels_batch_replay(stixels_batch *b, void *stream);
+
+/* Workgroups of the persistent launch last used, and the number of
+ * tasks (frame columns) of the last call. */
+int stixels_batch_info(const stixels_batch *b, int32_t *workgroups, int32_t *tasks);
+const char *stixels_batch_last_error(const stixels_batch *b);
+
+/* ------------------------------------------------------------------ debug
+ * Host copies of the handle's offline tables (Sec. 3.4), for parity tests.
+ * which = STIXELS_TABLE_*; bytes must equal the table's size:
+ *   SKY    float[d_range]                  cost of sky per pixel disparity
+ *   GROUND float[max_height][d_range]      ground cost per top-down image row
+ *   OBJECT float[d_range][d_range]         [f][d]: object of mean f, pixel disparity d
+ *   FG_HI  int32[max_height]               diving threshold per top-down row
+ *   FG_LO  int32[max_height]               gravity threshold per top-down row */
+enum { STIXELS_TABLE_SKY = 0, STIXELS_TABLE_GROUND = 1, STIXELS_TABLE_OBJECT = 2,
+       STIXELS_TABLE_FG_HI = 3, STIXELS_TABLE_FG_LO = 4 };
+int stixels_debug_table(const stixels_handle *h, int32_t which, void *host_dst, size_t bytes);
+
+/* The same tables built on the host from `params` alone, without a handle or
+ * a device (validation and range checks as in stixels_create; the error
+ * text is then available from stixels_last_error(NULL)). */
+int stixels_host_table(const stixels_params *params, int32_t which, void *host_dst, size_t bytes);
+
+/* Host copies of the intermediates of the last stixels_compute on this
+ * handle (synchronises `stream` first).  With ncols columns of height h:
+ *   REDUCED  int16[ncols][h]               reduced bottom-up disparities, -1 invalid
+ *   PREFIX   float[4][ncols][h+1]          ground, sky, 2*sum(q)+count, 2*count prefixes
+ *   RANGE    int32[ncols][2]               smallest / largest valid q of each column
+ *   OBJECT_PREFIX float[ncols][d_range][h+1] object prefix table, row f - fmin of
+ *                                          each column (rows past fmax unused) */
+enum { STIXELS_STAGE_REDUCED = 0, STIXELS_STAGE_PREFIX = 1, STIXELS_STAGE_RANGE = 2,
+       STIXELS_STAGE_OBJECT_PREFIX = 3 };
+int stixels_debug_stage(const stixels_handle *h, int32_t which, void *host_dst, size_t bytes,
+                        void *stream);
+
+/* Exhaustive device check of the rounded object mean used by the recurrence:
+ * for every count n in 1..max_height and every sum S in 0..n*(d_range-1),
+ * compares the kernel's floor((2S+n)/(2n)) against integer division and
+ * writes the number of mismatches to *host_mismatches.  Synchronous. */
+int stixels_selftest_mean(int32_t d_range, int32_t max_height, int64_t *host_mismatches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STIXELS_H */

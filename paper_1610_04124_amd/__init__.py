@@ -1,0 +1,22 @@
+"""gfx950-native multi-stixel segmentation (Hernandez-Juarez et al.,
+"GPU-accelerated real-time stixel computation").
+
+The work runs in hand-written HIP kernels behind the C ABI of
+``include/stixels.h``; this package is the argument-marshalling binding.
+"""
+
+from .binding import (  # noqa: F401
+    EXPORTS,
+    Batch,
+    FrameOutput,
+    Stixels,
+    StixelsError,
+    decode_records,
+    host_table,
+    lib,
+    selftest_mean,
+    status_string,
+)
+
+__all__ = ["Batch", "Stixels", "FrameOutput", "StixelsError", "decode_records", "host_table", "lib", "selftest_mean",
+           "status_string", "EXPORTS"]

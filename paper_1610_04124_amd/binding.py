@@ -1,0 +1,397 @@
+"""Thin ctypes binding of ``libstixels.so`` (include/stixels.h).
+
+Argument marshalling only: every step of the segmentation runs in the HIP
+kernels behind the C ABI.  Device buffers are torch tensors on a ROCm device;
+streams are torch.cuda streams (HIP streams under ROCm).  When the shared
+library is missing, loading fails loudly: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstixels.so")
+
+OK, E_INVALID_ARG, E_RANGE, E_HIP, E_NOMEM = 0, -1, -2, -3, -4
+TABLE_SKY, TABLE_GROUND, TABLE_OBJECT, TABLE_FG_HI, TABLE_FG_LO = range(5)
+STAGE_REDUCED, STAGE_PREFIX, STAGE_RANGE, STAGE_OBJECT_PREFIX = range(4)
+
+#: every entry point declared in include/stixels.h
+EXPORTS = (
+    "stixels_create", "stixels_destroy", "stixels_num_columns", "stixels_output_capacity",
+    "stixels_compute", "stixels_last_error", "stixels_status_string",
+    "stixels_batch_create", "stixels_batch_destroy", "stixels_batch_compute",
+    "stixels_batch_capture", "stixels_batch_replay", "stixels_batch_info",
+    "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
+    "stixels_debug_stage", "stixels_selftest_mean",
+)
+
+
+class StixelsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Camera(C.Structure):
+    _fields_ = [("focal_px", C.c_double), ("baseline_m", C.c_double),
+                ("cam_height_m", C.c_double), ("horizon_row", C.c_double),
+                ("pitch_rad", C.c_double)]
+
+
+class Model(C.Structure):
+    _fields_ = [("p_out", C.c_double), ("sigma_disp", C.c_double), ("sigma_sky", C.c_double),
+                ("ground_slope_noise", C.c_double), ("object_depth_extent_m", C.c_double),
+                ("bic_cost", C.c_double), ("first_cost", C.c_double * 3),
+                ("trans_cost", (C.c_double * 3) * 3), ("ordering_cost", C.c_double),
+                ("gravity_cost", C.c_double), ("gravity_tol_px", C.c_double),
+                ("diving_cost", C.c_double), ("diving_tol_px", C.c_double),
+                ("ordering_tol_px", C.c_int32), ("reserved0", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("camera", Camera), ("model", Model), ("stixel_width", C.c_int32),
+                ("max_disparity", C.c_int32), ("max_width", C.c_int32),
+                ("max_height", C.c_int32), ("max_stixels_per_column", C.c_int32),
+                ("reduce_mode", C.c_int32), ("cost_grid_log2", C.c_int32),
+                ("reserved0", C.c_int32)]
+
+
+class Output(C.Structure):
+    _fields_ = [("counts", C.c_void_p), ("records", C.c_void_p), ("total_cost", C.c_void_p),
+                ("overflow", C.c_void_p), ("capacity", C.c_int32), ("reserved0", C.c_int32)]
+
+
+class Job(C.Structure):
+    _fields_ = [("handle", C.c_void_p), ("d_disparity", C.c_void_p), ("width", C.c_int32),
+                ("height", C.c_int32), ("out", Output)]
+
+
+class BatchConfig(C.Structure):
+    _fields_ = [("max_jobs", C.c_int32), ("max_tasks", C.c_int32), ("max_height", C.c_int32),
+                ("max_disparity", C.c_int32), ("workgroups", C.c_int32), ("reserved0", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1610_04124_amd.build` (no CPU fallback exists)")
+        # torch ships its own HIP runtime (SONAME libamdhip64.so.7) and loads
+        # it under another file name; importing torch first lets this
+        # library's libamdhip64.so.7 dependency bind to that same runtime, so
+        # the process holds one HIP runtime and shares devices and streams.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, i32, P = C.c_void_p, C.c_int32, C.POINTER
+        L.stixels_create.argtypes = [P(Params), P(vp)]
+        L.stixels_destroy.argtypes = [vp]
+        L.stixels_num_columns.argtypes = [vp, i32, P(i32)]
+        L.stixels_output_capacity.argtypes = [vp, i32, P(i32)]
+        L.stixels_compute.argtypes = [vp, vp, i32, i32, vp, P(Output)]
+        L.stixels_last_error.argtypes = [vp]
+        L.stixels_last_error.restype = C.c_char_p
+        L.stixels_status_string.argtypes = [C.c_int]
+        L.stixels_status_string.restype = C.c_char_p
+        L.stixels_debug_table.argtypes = [vp, i32, vp, C.c_size_t]
+        L.stixels_host_table.argtypes = [P(Params), i32, vp, C.c_size_t]
+        L.stixels_debug_stage.argtypes = [vp, i32, vp, C.c_size_t, vp]
+        L.stixels_selftest_mean.argtypes = [i32, i32, P(C.c_int64)]
+        L.stixels_batch_create.argtypes = [P(BatchConfig), P(vp)]
+        L.stixels_batch_destroy.argtypes = [vp]
+        L.stixels_batch_compute.argtypes = [vp, P(Job), i32, vp]
+        L.stixels_batch_capture.argtypes = [vp, P(Job), i32, vp]
+        L.stixels_batch_replay.argtypes = [vp, vp]
+        L.stixels_batch_info.argtypes = [vp, P(i32), P(i32)]
+        L.stixels_batch_last_error.argtypes = [vp]
+        L.stixels_batch_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def to_params(params: dict) -> Params:
+    p = Params()
+    for k in ("focal_px", "baseline_m", "cam_height_m", "horizon_row", "pitch_rad"):
+        setattr(p.camera, k, float(params["camera"][k]))
+    m = params["model"]
+    for k in ("p_out", "sigma_disp", "sigma_sky", "ground_slope_noise", "object_depth_extent_m",
+              "bic_cost", "ordering_cost", "gravity_cost", "gravity_tol_px", "diving_cost",
+              "diving_tol_px"):
+        setattr(p.model, k, float(m[k]))
+    p.model.ordering_tol_px = int(m["ordering_tol_px"])
+    for a in range(3):
+        p.model.first_cost[a] = float(m["first_cost"][a])
+        for b in range(3):
+            p.model.trans_cost[a][b] = float(m["trans_cost"][a][b])
+    for k in ("stixel_width", "max_disparity", "max_width", "max_height",
+              "max_stixels_per_column", "reduce_mode", "cost_grid_log2"):
+        setattr(p, k, int(params[k]))
+    return p
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _check_device_tensor(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor")
+
+
+class FrameOutput:
+    """Caller-owned device output of one frame (torch tensors)."""
+
+    def __init__(self, ncols: int, capacity: int, device):
+        import torch
+        self.ncols, self.capacity = int(ncols), int(capacity)
+        self.counts = torch.zeros(ncols, dtype=torch.int32, device=device)
+        self.records = torch.zeros((ncols, capacity, 3), dtype=torch.int32, device=device)
+        self.total = torch.zeros(ncols, dtype=torch.float32, device=device)
+        self.overflow = torch.zeros(ncols, dtype=torch.uint8, device=device)
+
+    def struct(self) -> Output:
+        o = Output()
+        o.counts = self.counts.data_ptr()
+        o.records = self.records.data_ptr()
+        o.total_cost = self.total.data_ptr()
+        o.overflow = self.overflow.data_ptr()
+        o.capacity = self.capacity
+        return o
+
+    def to_host(self) -> dict:
+        """Decoded host copy: counts, records (structured, bottom-up), total, overflow."""
+        rec = self.records.cpu().numpy()
+        return dict(counts=self.counts.cpu().numpy(), records=decode_records(rec),
+                    total=self.total.cpu().numpy(), overflow=self.overflow.cpu().numpy())
+
+
+RECORD_DTYPE = np.dtype([("v_bottom", np.int32), ("v_top", np.int32), ("cls", np.int32),
+                         ("disparity", np.int32), ("cost", np.float32)])
+
+
+def decode_records(raw: np.ndarray) -> np.ndarray:
+    """[..., 3] int32 words (stixels_record) -> structured array."""
+    raw = np.ascontiguousarray(raw, dtype=np.int32)
+    w = raw.view(np.uint32)
+    out = np.zeros(raw.shape[:-1], RECORD_DTYPE)
+    out["v_bottom"] = (w[..., 0] & 0xFFFF).astype(np.int16)
+    out["v_top"] = (w[..., 0] >> 16).astype(np.int16)
+    out["cls"] = w[..., 1] & 0xFF
+    out["disparity"] = (w[..., 1] >> 8) & 0xFF
+    out["cost"] = raw[..., 2].view(np.float32)
+    return out
+
+
+class Stixels:
+    """One camera model: the resident offline tables and a per-frame workspace."""
+
+    def __init__(self, params: dict):
+        self.params = params
+        self._p = to_params(params)
+        h = C.c_void_p()
+        rc = lib().stixels_create(C.byref(self._p), C.byref(h))
+        if rc != OK:
+            raise StixelsError(rc, "stixels_create: " + lib().stixels_last_error(None).decode())
+        self.h = h
+        self.s = int(params["stixel_width"])
+        self.D = int(params["max_disparity"])
+        self.max_height = int(params["max_height"])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().stixels_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc, what):
+        raise StixelsError(rc, f"{what}: " + lib().stixels_last_error(self.h).decode())
+
+    def num_columns(self, width: int) -> int:
+        n = C.c_int32()
+        rc = lib().stixels_num_columns(self.h, int(width), C.byref(n))
+        if rc != OK:
+            self._err(rc, "stixels_num_columns")
+        return n.value
+
+    def capacity(self, height: int) -> int:
+        n = C.c_int32()
+        rc = lib().stixels_output_capacity(self.h, int(height), C.byref(n))
+        if rc != OK:
+            self._err(rc, "stixels_output_capacity")
+        return n.value
+
+    def new_output(self, width: int, height: int, device=None) -> FrameOutput:
+        import torch
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        return FrameOutput(self.num_columns(width), self.capacity(height), dev)
+
+    def compute(self, disp, out: FrameOutput | None = None, stream=None) -> FrameOutput:
+        """Enqueue the segmentation of one device frame [height, width] float32."""
+        import torch
+        _check_device_tensor(disp, torch.float32, "disparity")
+        H, W = disp.shape
+        if out is None:
+            out = self.new_output(W, H, disp.device)
+        o = out.struct()
+        rc = lib().stixels_compute(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
+                                   _stream_ptr(stream), C.byref(o))
+        if rc != OK:
+            self._err(rc, "stixels_compute")
+        return out
+
+    def compute_raw(self, disp_ptr: int, W: int, H: int, out: Output, stream_ptr) -> None:
+        rc = lib().stixels_compute(self.h, C.c_void_p(disp_ptr), int(W), int(H), stream_ptr,
+                                   C.byref(out))
+        if rc != OK:
+            self._err(rc, "stixels_compute")
+
+    # ------------------------------------------------------------- debug
+    def debug_table(self, which: int) -> np.ndarray:
+        shape, dt = _table_shape(which, self.D, self.max_height)
+        a = np.zeros(shape, dt)
+        rc = lib().stixels_debug_table(self.h, int(which), a.ctypes.data, a.nbytes)
+        if rc != OK:
+            self._err(rc, "stixels_debug_table")
+        return a
+
+    def debug_stage(self, which: int, W: int, H: int, stream=None) -> np.ndarray:
+        ncols = W // self.s
+        shape, dt = {STAGE_REDUCED: ((ncols, H), np.int16),
+                     STAGE_PREFIX: ((4, ncols, H + 1), np.float32),
+                     STAGE_RANGE: ((ncols, 2), np.int32),
+                     STAGE_OBJECT_PREFIX: ((ncols, self.D, H + 1), np.float32)}[which]
+        a = np.zeros(shape, dt)
+        rc = lib().stixels_debug_stage(self.h, int(which), a.ctypes.data, a.nbytes,
+                                       _stream_ptr(stream))
+        if rc != OK:
+            self._err(rc, "stixels_debug_stage")
+        return a
+
+
+def _table_shape(which, D, Hm):
+    return {TABLE_SKY: ((D,), np.float32), TABLE_GROUND: ((Hm, D), np.float32),
+            TABLE_OBJECT: ((D, D), np.float32), TABLE_FG_HI: ((Hm,), np.int32),
+            TABLE_FG_LO: ((Hm,), np.int32)}[which]
+
+
+def host_table(params: dict, which: int) -> np.ndarray:
+    """An offline table built on the host by the library, without a device."""
+    shape, dt = _table_shape(which, int(params["max_disparity"]), int(params["max_height"]))
+    a = np.zeros(shape, dt)
+    p = to_params(params)
+    rc = lib().stixels_host_table(C.byref(p), int(which), a.ctypes.data, a.nbytes)
+    if rc != OK:
+        raise StixelsError(rc, "stixels_host_table: " + lib().stixels_last_error(None).decode())
+    return a
+
+
+def selftest_mean(d_range: int, max_height: int) -> int:
+    n = C.c_int64(-1)
+    rc = lib().stixels_selftest_mean(int(d_range), int(max_height), C.byref(n))
+    if rc != OK:
+        raise StixelsError(rc, "stixels_selftest_mean")
+    return n.value
+
+
+def status_string(code: int) -> str:
+    return lib().stixels_status_string(int(code)).decode()
+
+
+def finite(x):
+    return x if math.isfinite(x) else math.inf
+
+
+class Batch:
+    """Persistent batched launch over many frames (possibly different cameras,
+    sizes and stixel widths); see stixels_batch_* in include/stixels.h."""
+
+    def __init__(self, max_jobs: int, max_tasks: int, max_height: int, max_disparity: int,
+                 workgroups: int = 0):
+        cfg = BatchConfig()
+        cfg.max_jobs, cfg.max_tasks = int(max_jobs), int(max_tasks)
+        cfg.max_height, cfg.max_disparity = int(max_height), int(max_disparity)
+        cfg.workgroups = int(workgroups)
+        b = C.c_void_p()
+        rc = lib().stixels_batch_create(C.byref(cfg), C.byref(b))
+        if rc != OK:
+            raise StixelsError(rc, "stixels_batch_create")
+        self.b = b
+        self.cfg = cfg
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().stixels_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _err(self, rc, what):
+        raise StixelsError(rc, f"{what}: " + lib().stixels_batch_last_error(self.b).decode())
+
+    @staticmethod
+    def make_jobs(items):
+        """items: sequence of (Stixels, device frame tensor [H, W], FrameOutput)."""
+        import torch
+        arr = (Job * len(items))()
+        keep = []
+        for i, (h, disp, out) in enumerate(items):
+            _check_device_tensor(disp, torch.float32, "disparity")
+            H, W = disp.shape
+            arr[i].handle = h.h
+            arr[i].d_disparity = disp.data_ptr()
+            arr[i].width, arr[i].height = int(W), int(H)
+            arr[i].out = out.struct()
+            keep.append((h, disp, out))
+        return arr, keep
+
+    def compute(self, items, stream=None):
+        arr, keep = self.make_jobs(items)
+        self._keep = keep
+        rc = lib().stixels_batch_compute(self.b, arr, len(arr), _stream_ptr(stream))
+        if rc != OK:
+            self._err(rc, "stixels_batch_compute")
+
+    def capture(self, items, stream=None):
+        arr, keep = self.make_jobs(items)
+        self._keep = keep
+        rc = lib().stixels_batch_capture(self.b, arr, len(arr), _stream_ptr(stream))
+        if rc != OK:
+            self._err(rc, "stixels_batch_capture")
+
+    def replay(self, stream=None):
+        rc = lib().stixels_batch_replay(self.b, _stream_ptr(stream))
+        if rc != OK:
+            self._err(rc, "stixels_batch_replay")
+
+    def info(self):
+        g, t = C.c_int32(), C.c_int32()
+        rc = lib().stixels_batch_info(self.b, C.byref(g), C.byref(t))
+        if rc != OK:
+            self._err(rc, "stixels_batch_info")
+        return g.value, t.value

@@ -1,0 +1,370 @@
+// api.hip -- C ABI of the stixel library: handle creation (offline tables of
+// Sec. 3.4 built in FP64 on the host, rounded to the cost grid, made resident
+// in HBM), the per-frame compute entry point and the debug exports.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "handle.h"
+#include "launch.h"
+#include "stixels.h"
+
+using namespace stx;
+
+namespace {
+
+int fail(stixels_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+// ------------------------------------------------------------------ Eq. 4
+double gauss_cdf(double x) { return 0.5 * std::erfc(-x / std::sqrt(2.0)); }
+
+// Per-pixel data cost of disparity d against a model disparity mu with
+// standard deviation sigma: the min of the uniform-outlier cost and the
+// Gaussian cost, the Gaussian normalised by its mass on [0, d_range].
+double pixel_cost(double d, double mu, double sigma, double p_out, double d_range) {
+    const double c_out = std::log(d_range) - std::log(p_out);
+    const double mass = gauss_cdf((d_range - mu) / sigma) - gauss_cdf(-mu / sigma);
+    const double g = std::log(mass) + std::log(sigma * std::sqrt(2.0 * M_PI)) -
+                     std::log(1.0 - p_out) + (d - mu) * (d - mu) / (2.0 * sigma * sigma);
+    if (!std::isfinite(g)) return c_out;
+    return g < c_out ? g : c_out;
+}
+
+double to_grid(double x, int g) {
+    if (!std::isfinite(x)) return x;
+    return std::ldexp(std::rint(std::ldexp(x, g)), -g);
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+int validate(const stixels_params* p, std::string& why) {
+    const stixels_camera& c = p->camera;
+    const stixels_model& m = p->model;
+    auto bad = [&](const char* w) { why = w; return STIXELS_E_INVALID_ARG; };
+    if (!(c.focal_px > 0 && c.baseline_m > 0 && c.cam_height_m > 0 && std::isfinite(c.pitch_rad)))
+        return bad("camera focal, baseline and height must be > 0, pitch finite");
+    if (!std::isfinite(c.horizon_row) || std::fabs(c.horizon_row) > 1048576.0 ||
+        std::ldexp(c.horizon_row, 8) != std::rint(std::ldexp(c.horizon_row, 8)))
+        return bad("horizon_row must be a multiple of 1/256 with |horizon_row| <= 2^20");
+    if (!(m.p_out > 0 && m.p_out < 1)) return bad("p_out must lie in (0, 1)");
+    if (!(m.sigma_disp > 0 && m.sigma_sky > 0 && std::isfinite(m.sigma_disp) &&
+          std::isfinite(m.sigma_sky)))
+        return bad("sigma_disp and sigma_sky must be finite and > 0");
+    if (!finite_nonneg(m.ground_slope_noise) || !finite_nonneg(m.object_depth_extent_m))
+        return bad("ground_slope_noise and object_depth_extent_m must be finite and >= 0");
+    if (!finite_nonneg(m.bic_cost) || !finite_nonneg(m.ordering_cost) ||
+        !finite_nonneg(m.gravity_cost) || !finite_nonneg(m.diving_cost) ||
+        !finite_nonneg(m.gravity_tol_px) || !finite_nonneg(m.diving_tol_px) ||
+        m.ordering_tol_px < 0)
+        return bad("prior costs and tolerances must be finite and >= 0");
+    for (int a = 0; a < 3; ++a) {
+        if (!finite_nonneg(m.first_cost[a])) return bad("first_cost must be finite and >= 0");
+        for (int b = 0; b < 3; ++b) {
+            const double t = m.trans_cost[a][b];
+            if (!(t >= 0.0)) return bad("trans_cost must be >= 0 (INFINITY = forbidden)");
+        }
+        if (!std::isfinite(m.trans_cost[a][STIXELS_OBJECT]))
+            return bad("trans_cost[*][object] must be finite");
+    }
+    if (p->stixel_width < 1 || p->stixel_width > kMaxStixelWidth)
+        return bad("stixel_width must lie in 1..16");
+    if (p->max_disparity < 2 || p->max_disparity > kMaxDisparity)
+        return bad("max_disparity must lie in 2..256");
+    if (p->max_height < 1 || p->max_height > kMaxHeight) return bad("max_height must lie in 1..1024");
+    if (p->max_width < p->stixel_width) return bad("max_width must be >= stixel_width");
+    if (p->max_stixels_per_column < 0) return bad("max_stixels_per_column must be >= 0");
+    if (p->reduce_mode != 0 && p->reduce_mode != 1) return bad("reduce_mode must be 0 or 1");
+    if (p->cost_grid_log2 < 0 || p->cost_grid_log2 > 12) return bad("cost_grid_log2 must lie in 0..12");
+    if ((long long)p->max_height * p->max_disparity > (1LL << 20)) {
+        why = "max_height * max_disparity must not exceed 2^20 (rounded-mean division bound)";
+        return STIXELS_E_RANGE;
+    }
+    return STIXELS_OK;
+}
+
+template <typename T>
+int upload(stixels_handle* h, T** dst, const std::vector<T>& src) {
+    if (hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T)) != hipSuccess)
+        return fail(h, STIXELS_E_NOMEM, "hipMalloc of a table failed");
+    if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(h, STIXELS_E_HIP, "hipMemcpy of a table failed");
+    return STIXELS_OK;
+}
+
+void release(stixels_handle* h) {
+    (void)hipFree(h->d_sky);
+    (void)hipFree(h->d_ground);
+    (void)hipFree(h->d_object_t);
+    (void)hipFree(h->d_fg_hi);
+    (void)hipFree(h->d_fg_lo);
+    (void)hipFree(h->d_q);
+    (void)hipFree(h->d_prefix);
+    (void)hipFree(h->d_range);
+    (void)hipFree(h->d_po);
+}
+
+// Offline tables (Sec. 3.4) in FP64, rounded to the grid and stored as FP32.
+int build_tables(stixels_handle* h) {
+    const stixels_params& p = h->p;
+    const stixels_model& m = p.model;
+    const int D = h->D, Hmax = h->Hmax, g = p.cost_grid_log2;
+    const double dr = (double)D;
+    const double hr = p.camera.horizon_row;
+    const double alpha = p.camera.baseline_m * std::cos(p.camera.pitch_rad) / p.camera.cam_height_m;
+    double cmax = 0.0;
+    auto keep = [&](double v) {
+        cmax = std::fmax(cmax, std::fabs(v));
+        return (float)v;
+    };
+    h->sky.resize(D);
+    for (int d = 0; d < D; ++d)
+        h->sky[d] = keep(to_grid(pixel_cost(d, 0.0, m.sigma_sky, m.p_out, dr), g));
+    // ground rows by top-down image row r: model disparity alpha (r - horizon),
+    // zero (never used) above the horizon
+    h->ground.assign((size_t)Hmax * D, 0.0f);
+    h->fg_hi.resize(Hmax);
+    h->fg_lo.resize(Hmax);
+    for (int r = 0; r < Hmax; ++r) {
+        const double mu = alpha * ((double)r - hr);
+        if ((double)r >= hr) {
+            const double e = m.ground_slope_noise * mu;
+            const double sg = std::sqrt(m.sigma_disp * m.sigma_disp + e * e);
+            for (int d = 0; d < D; ++d)
+                h->ground[(size_t)r * D + d] = keep(to_grid(pixel_cost(d, mu, sg, m.p_out, dr), g));
+        }
+        h->fg_hi[r] = (int32_t)std::floor(mu + m.diving_tol_px);
+        h->fg_lo[r] = (int32_t)std::ceil(mu - m.gravity_tol_px);
+    }
+    // object table stored as [f][d]: one row per model mean f
+    h->object_t.resize((size_t)D * D);
+    for (int f = 0; f < D; ++f) {
+        const double e = (double)f * (double)f * m.object_depth_extent_m /
+                         (p.camera.focal_px * p.camera.baseline_m);
+        const double so = std::sqrt(m.sigma_disp * m.sigma_disp + e * e);
+        for (int d = 0; d < D; ++d)
+            h->object_t[(size_t)f * D + d] = keep(to_grid(pixel_cost(d, f, so, m.p_out, dr), g));
+    }
+    // priors
+    const double beta = to_grid(m.bic_cost, g);
+    double fmaxp = 0.0, tmaxp = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double f = to_grid(m.first_cost[a], g) + beta;
+        h->prior.first[a] = (float)f;
+        fmaxp = std::fmax(fmaxp, f);
+        for (int b = 0; b < 3; ++b) {
+            const double t = to_grid(m.trans_cost[a][b], g) + beta;
+            h->prior.trans[a][b] = (float)t;
+            if (std::isfinite(t)) tmaxp = std::fmax(tmaxp, t);
+        }
+    }
+    h->prior.c_ord = (float)to_grid(m.ordering_cost, g);
+    h->prior.c_grav = (float)to_grid(m.gravity_cost, g);
+    h->prior.c_dive = (float)to_grid(m.diving_cost, g);
+    h->prior.tau_ord = m.ordering_tol_px;
+    h->prior.mean_eps = (float)std::ldexp((double)D, -22);
+    // exactness: every prefix, cost and intermediate of the recurrence is a
+    // multiple of 2^-g bounded by 2 (h+1) cmax plus the priors
+    const double bound = 2.0 * (Hmax + 1) * cmax + fmaxp + tmaxp + h->prior.c_ord +
+                         h->prior.c_grav + h->prior.c_dive;
+    if (!(bound < std::ldexp(1.0, 24 - g))) {
+        char buf[200];
+        snprintf(buf, sizeof buf,
+                 "cost range %.1f reaches 2^(24-g) = %.0f: FP32 would not be exact on the grid",
+                 bound, std::ldexp(1.0, 24 - g));
+        return fail(h, STIXELS_E_RANGE, buf);
+    }
+    return STIXELS_OK;
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+extern "C" {
+
+int stixels_create(const stixels_params* params, stixels_handle** out) {
+    if (!params || !out) return STIXELS_E_INVALID_ARG;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(params, why);
+    if (rc != STIXELS_OK) {
+        g_create_error = why;
+        return rc;
+    }
+    stixels_handle* h = new (std::nothrow) stixels_handle;
+    if (!h) return STIXELS_E_NOMEM;
+    h->p = *params;
+    h->D = params->max_disparity;
+    h->Hmax = params->max_height;
+    h->Wmax = params->max_width;
+    h->s = params->stixel_width;
+    h->ncols_max = h->Wmax / h->s;
+    rc = build_tables(h);
+    if (rc == STIXELS_OK && hipGetDevice(&h->device) != hipSuccess)
+        rc = fail(h, STIXELS_E_HIP, "no HIP device");
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_sky, h->sky);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_ground, h->ground);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_object_t, h->object_t);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_hi, h->fg_hi);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_lo, h->fg_lo);
+    if (rc == STIXELS_OK) {
+        const size_t nc = (size_t)h->ncols_max, H1 = (size_t)h->Hmax + 1;
+        bool ok = hipMalloc(reinterpret_cast<void**>(&h->d_q), nc * h->Hmax * sizeof(int16_t)) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_prefix), 4 * nc * H1 * sizeof(float)) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_range), 2 * nc * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_po), nc * h->D * H1 * sizeof(float)) == hipSuccess;
+        if (!ok) rc = fail(h, STIXELS_E_NOMEM, "hipMalloc of the frame workspace failed");
+    }
+    if (rc != STIXELS_OK) {
+        g_create_error = h->err;
+        release(h);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return STIXELS_OK;
+}
+
+int stixels_destroy(stixels_handle* h) {
+    if (!h) return STIXELS_OK;
+    release(h);
+    delete h;
+    return STIXELS_OK;
+}
+
+int stixels_num_columns(const stixels_handle* h, int32_t width, int32_t* ncols) {
+    if (!h || !ncols || width < h->s) return STIXELS_E_INVALID_ARG;
+    *ncols = width / h->s;
+    return STIXELS_OK;
+}
+
+int stixels_output_capacity(const stixels_handle* h, int32_t height, int32_t* capacity) {
+    if (!h || !capacity || height < 1) return STIXELS_E_INVALID_ARG;
+    *capacity = h->p.max_stixels_per_column > 0 ? h->p.max_stixels_per_column : height;
+    return STIXELS_OK;
+}
+
+int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, int32_t height,
+                    void* stream, const stixels_output* out) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (!d_disparity || !out || !out->counts || !out->records || !out->total_cost ||
+        !out->overflow)
+        return fail(h, STIXELS_E_INVALID_ARG, "null input or output pointer");
+    if (width < h->s || width > h->Wmax)
+        return fail(h, STIXELS_E_INVALID_ARG, "width outside [stixel_width, max_width]");
+    if (height < 1 || height > h->Hmax)
+        return fail(h, STIXELS_E_INVALID_ARG, "height outside [1, max_height]");
+    if (out->capacity < 1) return fail(h, STIXELS_E_INVALID_ARG, "output capacity must be >= 1");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int ncols = width / h->s;
+    const int vtop = ground_top(h->p.camera.horizon_row, height);
+    DeviceModel m = device_model(h);
+    FrameWorkspace ws{h->d_q, h->d_prefix, h->d_range, h->d_po};
+    FrameOutput fo{out->counts, reinterpret_cast<uint32_t*>(out->records), out->total_cost,
+                   out->overflow, out->capacity};
+    hipError_t e = launch_reduce(m, d_disparity, width, height, ncols, ws.q, st);
+    if (e == hipSuccess) e = launch_tables(m, ws, height, ncols, vtop, st);
+    if (e == hipSuccess) e = launch_dp(m, ws, height, ncols, vtop, fo, st);
+    if (e != hipSuccess)
+        return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    h->last_W = width;
+    h->last_H = height;
+    return STIXELS_OK;
+}
+
+const char* stixels_last_error(const stixels_handle* h) {
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+const char* stixels_status_string(int code) {
+    switch (code) {
+        case STIXELS_OK: return "ok";
+        case STIXELS_E_INVALID_ARG: return "invalid argument";
+        case STIXELS_E_RANGE: return "parameters outside the exact cost range";
+        case STIXELS_E_HIP: return "HIP error";
+        case STIXELS_E_NOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+namespace {
+int copy_table(const stixels_handle* h, int32_t which, void* host_dst, size_t bytes) {
+    const void* src = nullptr;
+    size_t n = 0;
+    switch (which) {
+        case STIXELS_TABLE_SKY: src = h->sky.data(); n = h->sky.size() * 4; break;
+        case STIXELS_TABLE_GROUND: src = h->ground.data(); n = h->ground.size() * 4; break;
+        case STIXELS_TABLE_OBJECT: src = h->object_t.data(); n = h->object_t.size() * 4; break;
+        case STIXELS_TABLE_FG_HI: src = h->fg_hi.data(); n = h->fg_hi.size() * 4; break;
+        case STIXELS_TABLE_FG_LO: src = h->fg_lo.data(); n = h->fg_lo.size() * 4; break;
+        default: return STIXELS_E_INVALID_ARG;
+    }
+    if (bytes != n) return STIXELS_E_INVALID_ARG;
+    std::memcpy(host_dst, src, n);
+    return STIXELS_OK;
+}
+}  // namespace
+
+int stixels_debug_table(const stixels_handle* h, int32_t which, void* host_dst, size_t bytes) {
+    if (!h || !host_dst) return STIXELS_E_INVALID_ARG;
+    return copy_table(h, which, host_dst, bytes);
+}
+
+int stixels_host_table(const stixels_params* params, int32_t which, void* host_dst,
+                       size_t bytes) {
+    if (!params || !host_dst) return STIXELS_E_INVALID_ARG;
+    std::string why;
+    int rc = validate(params, why);
+    if (rc != STIXELS_OK) {
+        g_create_error = why;
+        return rc;
+    }
+    stixels_handle h;
+    h.p = *params;
+    h.D = params->max_disparity;
+    h.Hmax = params->max_height;
+    h.Wmax = params->max_width;
+    h.s = params->stixel_width;
+    rc = build_tables(&h);
+    if (rc != STIXELS_OK) {
+        g_create_error = h.err;
+        return rc;
+    }
+    return copy_table(&h, which, host_dst, bytes);
+}
+
+int stixels_debug_stage(const stixels_handle* h, int32_t which, void* host_dst, size_t bytes,
+                        void* stream) {
+    if (!h || !host_dst || h->last_H < 1) return STIXELS_E_INVALID_ARG;
+    const size_t ncols = (size_t)(h->last_W / h->s), H = (size_t)h->last_H;
+    const void* src = nullptr;
+    size_t n = 0;
+    switch (which) {
+        case STIXELS_STAGE_REDUCED: src = h->d_q; n = ncols * H * 2; break;
+        case STIXELS_STAGE_PREFIX: src = h->d_prefix; n = 4 * ncols * (H + 1) * 4; break;
+        case STIXELS_STAGE_RANGE: src = h->d_range; n = 2 * ncols * 4; break;
+        case STIXELS_STAGE_OBJECT_PREFIX: src = h->d_po; n = ncols * h->D * (H + 1) * 4; break;
+        default: return STIXELS_E_INVALID_ARG;
+    }
+    if (bytes != n) return STIXELS_E_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return STIXELS_E_HIP;
+    if (hipMemcpy(host_dst, src, n, hipMemcpyDeviceToHost) != hipSuccess) return STIXELS_E_HIP;
+    return STIXELS_OK;
+}
+
+int stixels_selftest_mean(int32_t d_range, int32_t max_height, int64_t* host_mismatches) {
+    if (!host_mismatches || d_range < 2 || d_range > kMaxDisparity || max_height < 1 ||
+        max_height > kMaxHeight || (long long)max_height * d_range > (1LL << 20))
+        return STIXELS_E_INVALID_ARG;
+    return run_selftest_mean(d_range, max_height, host_mismatches) == hipSuccess ? STIXELS_OK
+                                                                                  : STIXELS_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,500 @@
+// batch.hip -- many frames in one persistent fused launch.
+//
+// Every (frame, column) pair is a task.  The host orders tasks by decreasing
+// frame height (the recurrence costs O(h^2) per column, Sec. 3.3), so the
+// longest columns start first, and resident single-wave workgroups pull
+// tasks from a device counter until the list is exhausted.  Each task runs
+// the whole per-column pipeline of Sec. 4 without leaving the workgroup:
+// strip reduction into LDS, the prefix tables and object prefix rows into
+// the workgroup's own scratch slot (written and re-read by the same wave,
+// so they stay in L2), then the recurrence and backtracking of dp_column.h.
+// Results are bit-identical to the per-frame kernels: the arithmetic is the
+// same exact grid arithmetic, only the schedule differs.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dp_column.h"
+#include "handle.h"
+#include "launch.h"
+#include "stixels.h"
+
+using namespace stx;
+
+namespace {
+
+struct JobDesc {
+    const float* disp;
+    const float* sky;
+    const float* ground;
+    const float* object_t;
+    const int32_t* fg_hi;
+    const int32_t* fg_lo;
+    int32_t* counts;
+    uint32_t* records;
+    float* total;
+    uint8_t* overflow;
+    int W, H, s, ncols, D, vtop, reduce_mode, cap;
+    Prior prior;
+};
+
+__device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D) {
+    switch (s) {
+#define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D);
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return -1;
+    }
+}
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+__global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
+
+template <int S>
+__global__ __launch_bounds__(64) void batch_kernel(const JobDesc* __restrict__ jobs,
+                                                   const int2* __restrict__ tasks, int ntasks,
+                                                   unsigned int* counter, float* scratch,
+                                                   long long scratch_stride) {
+    __shared__ int16_t qs[kMaxHeight];
+    const int lane = threadIdx.x;
+    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = (int)atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        const JobDesc& J = jobs[tk.x];
+        const int H = J.H, D = J.D, col = tk.y, stride = H + 1;
+
+        // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
+        int lmin = INT_MAX, lmax = -1;
+        for (int base = 0; base < H; base += 64) {
+            const int v = base + lane;
+            if (v < H) {
+                const int r = H - 1 - v;
+                const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
+                                         J.reduce_mode, D);
+                qs[v] = (int16_t)x;
+                if (x >= 0) {
+                    lmin = min(lmin, x);
+                    lmax = max(lmax, x);
+                }
+            }
+        }
+        int fmin = wave_min_i(lmin), fmax = wave_max_i(lmax);
+        if (fmax < 0) {
+            fmin = 0;
+            fmax = 0;
+        }
+        __syncthreads();
+
+        // Sec. 4.2: prefix tables into the scratch slot
+        float* PG = ws;
+        float* PS = ws + stride;
+        float* PA = ws + 2 * stride;
+        float* PN = ws + 3 * stride;
+        float* PO = ws + 4 * stride;
+        if (lane == 0) {
+            PG[0] = 0.0f;
+            PS[0] = 0.0f;
+            PA[0] = 0.0f;
+            PN[0] = 0.0f;
+        }
+        float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+        for (int base = 0; base < H; base += 64) {
+            const int v = base + lane;
+            const int x = (v < H) ? (int)qs[v] : -1;
+            float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+            if (x >= 0) {
+                g = J.ground[(size_t)(H - 1 - v) * D + x];
+                sk = J.sky[x];
+                aa = (float)(2 * x + 1);
+                nn = 2.0f;
+            }
+            g = wave_inclusive_scan(g) + cg;
+            sk = wave_inclusive_scan(sk) + cs;
+            aa = wave_inclusive_scan(aa) + ca;
+            nn = wave_inclusive_scan(nn) + cn;
+            if (v < H) {
+                PG[v + 1] = g;
+                PS[v + 1] = sk;
+                PA[v + 1] = aa;
+                PN[v + 1] = nn;
+            }
+            cg = readlane_f(g, 63);
+            cs = readlane_f(sk, 63);
+            ca = readlane_f(aa, 63);
+            cn = readlane_f(nn, 63);
+        }
+        for (int f = fmin; f <= fmax; ++f) {
+            const float* orow = J.object_t + (size_t)f * D;
+            float* prow = PO + (size_t)(f - fmin) * stride;
+            if (lane == 0) prow[0] = 0.0f;
+            float carry = 0.0f;
+            for (int base = 0; base < H; base += 64) {
+                const int v = base + lane;
+                const int x = (v < H) ? (int)qs[v] : -1;
+                float o = (x >= 0) ? orow[x] : 0.0f;
+                o = wave_inclusive_scan(o) + carry;
+                if (v < H) prow[v + 1] = o;
+                carry = readlane_f(o, 63);
+            }
+        }
+        __syncthreads();   // the tables written above are read back below
+
+        // Sec. 4.3-4.4
+        ColumnIn in;
+        in.PG = PG;
+        in.PS = PS;
+        in.PA = PA;
+        in.PN2 = PN;
+        in.PO = PO;
+        in.fmin = fmin;
+        in.fmax = fmax;
+        in.fg_hi = J.fg_hi;
+        in.fg_lo = J.fg_lo;
+        ColumnOut out;
+        out.count = J.counts + col;
+        out.rec = J.records + (size_t)col * J.cap * 3;
+        out.total = J.total + col;
+        out.overflow = J.overflow + col;
+        out.cap = J.cap;
+        solve_column<S>(H, J.vtop, J.prior, in, out);
+        __syncthreads();   // every read of the slot completes before the next task rewrites it
+    }
+}
+
+template <int S>
+void* kernel_ptr() {
+    return reinterpret_cast<void*>(&batch_kernel<S>);
+}
+
+void* batch_kernel_for(int slots) {
+    switch (slots) {
+#define STX_CASE(n) case n: return kernel_ptr<n>();
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_batch(int slots, int grid, hipStream_t st, const JobDesc* jobs, const int2* tasks,
+                        int ntasks, unsigned int* counter, float* scratch, long long stride) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    switch (slots) {
+#define STX_CASE(n)                                                                        \
+    case n:                                                                                \
+        hipLaunchKernelGGL(batch_kernel<n>, dim3(grid), dim3(64), 0, st, jobs, tasks,      \
+                           ntasks, counter, scratch, stride);                              \
+        break;
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+struct stixels_batch {
+    stixels_batch_config cfg{};
+    int num_cu = 0;
+    // descriptors of the eager path and of the captured graph
+    JobDesc* d_jobs = nullptr;
+    int2* d_tasks = nullptr;
+    unsigned int* d_counter = nullptr;
+    JobDesc* d_jobs_g = nullptr;
+    int2* d_tasks_g = nullptr;
+    unsigned int* d_counter_g = nullptr;
+    float* d_scratch = nullptr;
+    size_t scratch_floats = 0;
+    JobDesc* h_jobs = nullptr;   // pinned staging
+    int2* h_tasks = nullptr;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int last_grid = 0, last_tasks = 0;
+    std::string err;
+};
+
+namespace {
+
+int bfail(stixels_batch* b, int code, const std::string& m) {
+    if (b) b->err = m;
+    return code;
+}
+
+int occupancy_grid(stixels_batch* b, int slots, int* grid) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots), 64, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        return bfail(b, STIXELS_E_HIP, "occupancy query failed");
+    *grid = per_cu * b->num_cu;
+    return STIXELS_OK;
+}
+
+// Validate the jobs and fill the pinned staging buffers: descriptors and the
+// task list in decreasing-height order.
+int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int* ntasks,
+          long long* stride) {
+    if (!jobs || n < 1 || n > b->cfg.max_jobs)
+        return bfail(b, STIXELS_E_INVALID_ARG, "job count outside [1, max_jobs]");
+    int hmax = 0, dmax = 0;
+    long long total = 0;
+    for (int i = 0; i < n; ++i) {
+        const stixels_job& j = jobs[i];
+        const stixels_handle* h = j.handle;
+        if (!h || !j.d_disparity || !j.out.counts || !j.out.records || !j.out.total_cost ||
+            !j.out.overflow)
+            return bfail(b, STIXELS_E_INVALID_ARG, "null handle, input or output in job " +
+                                                       std::to_string(i));
+        if (j.width < h->s || j.width > h->Wmax || j.height < 1 || j.height > h->Hmax ||
+            j.height > b->cfg.max_height || h->D > b->cfg.max_disparity || j.out.capacity < 1)
+            return bfail(b, STIXELS_E_INVALID_ARG, "job " + std::to_string(i) +
+                                                       " outside its handle's or the batch's limits");
+        hmax = std::max(hmax, (int)j.height);
+        dmax = std::max(dmax, h->D);
+        total += j.width / h->s;
+    }
+    if (total > b->cfg.max_tasks)
+        return bfail(b, STIXELS_E_INVALID_ARG, "more frame columns than max_tasks");
+    if (b->staged_pending) {
+        if (hipEventSynchronize(b->staged) != hipSuccess)
+            return bfail(b, STIXELS_E_HIP, "waiting for the previous upload failed");
+        b->staged_pending = false;
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return jobs[a].height > jobs[c].height; });
+    int t = 0;
+    for (int i = 0; i < n; ++i) {
+        const stixels_job& j = jobs[i];
+        const stixels_handle* h = j.handle;
+        JobDesc& d = b->h_jobs[i];
+        d.disp = j.d_disparity;
+        d.sky = h->d_sky;
+        d.ground = h->d_ground;
+        d.object_t = h->d_object_t;
+        d.fg_hi = h->d_fg_hi;
+        d.fg_lo = h->d_fg_lo;
+        d.counts = j.out.counts;
+        d.records = reinterpret_cast<uint32_t*>(j.out.records);
+        d.total = j.out.total_cost;
+        d.overflow = j.out.overflow;
+        d.W = j.width;
+        d.H = j.height;
+        d.s = h->s;
+        d.ncols = j.width / h->s;
+        d.D = h->D;
+        d.vtop = ground_top(h->p.camera.horizon_row, j.height);
+        d.reduce_mode = h->p.reduce_mode;
+        d.cap = j.out.capacity;
+        d.prior = h->prior;
+    }
+    for (int oi = 0; oi < n; ++oi) {
+        const int i = order[oi];
+        const int nc = b->h_jobs[i].ncols;
+        for (int c = 0; c < nc; ++c) b->h_tasks[t++] = make_int2(i, c);
+    }
+    *slots = (hmax + 63) / 64;
+    *ntasks = t;
+    *stride = (long long)(4 + dmax) * (hmax + 1);
+    return STIXELS_OK;
+}
+
+int choose_grid(stixels_batch* b, int slots, long long stride, int ntasks, int* grid) {
+    int g = 0;
+    int rc = occupancy_grid(b, slots, &g);
+    if (rc != STIXELS_OK) return rc;
+    if (b->cfg.workgroups > 0) g = std::min(g, (int)b->cfg.workgroups);
+    const long long by_scratch = (long long)(b->scratch_floats / (size_t)stride);
+    g = (int)std::min<long long>(g, by_scratch);
+    g = std::min(g, ntasks);
+    if (g < 1) return bfail(b, STIXELS_E_INVALID_ARG, "batch scratch too small for these jobs");
+    *grid = g;
+    return STIXELS_OK;
+}
+
+int upload(stixels_batch* b, JobDesc* dj, int2* dt, int n, int ntasks, hipStream_t st) {
+    if (hipMemcpyAsync(dj, b->h_jobs, sizeof(JobDesc) * n, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(dt, b->h_tasks, sizeof(int2) * ntasks, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        return bfail(b, STIXELS_E_HIP, "descriptor upload failed");
+    if (hipEventRecord(b->staged, st) != hipSuccess)
+        return bfail(b, STIXELS_E_HIP, "event record failed");
+    b->staged_pending = true;
+    return STIXELS_OK;
+}
+
+void destroy_graph(stixels_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
+    if (!cfg || !out) return STIXELS_E_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->max_jobs < 1 || cfg->max_tasks < 1 || cfg->max_height < 1 ||
+        cfg->max_height > kMaxHeight || cfg->max_disparity < 2 ||
+        cfg->max_disparity > kMaxDisparity || cfg->workgroups < 0)
+        return STIXELS_E_INVALID_ARG;
+    stixels_batch* b = new (std::nothrow) stixels_batch;
+    if (!b) return STIXELS_E_NOMEM;
+    b->cfg = *cfg;
+    int dev = 0;
+    int rc = STIXELS_OK;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess)
+        rc = STIXELS_E_HIP;
+    int grid = 0;
+    const int slots = (cfg->max_height + 63) / 64;
+    if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, &grid);
+    if (rc == STIXELS_OK && cfg->workgroups > 0) grid = std::min(grid, (int)cfg->workgroups);
+    if (rc == STIXELS_OK) {
+        b->scratch_floats = (size_t)grid * (size_t)(4 + cfg->max_disparity) *
+                            (size_t)(cfg->max_height + 1);
+        const bool ok =
+            hipMalloc(reinterpret_cast<void**>(&b->d_jobs), sizeof(JobDesc) * cfg->max_jobs) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_tasks), sizeof(int2) * cfg->max_tasks) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_counter), sizeof(unsigned int)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_jobs_g), sizeof(JobDesc) * cfg->max_jobs) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_tasks_g), sizeof(int2) * cfg->max_tasks) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_counter_g), sizeof(unsigned int)) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_scratch), sizeof(float) * b->scratch_floats) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_jobs), sizeof(JobDesc) * cfg->max_jobs, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_tasks), sizeof(int2) * cfg->max_tasks, hipHostMallocDefault) == hipSuccess &&
+            hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
+        if (!ok) rc = STIXELS_E_NOMEM;
+    }
+    if (rc != STIXELS_OK) {
+        stixels_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return STIXELS_OK;
+}
+
+int stixels_batch_destroy(stixels_batch* b) {
+    if (!b) return STIXELS_OK;
+    if (b->staged_pending) (void)hipEventSynchronize(b->staged);
+    destroy_graph(b);
+    (void)hipFree(b->d_jobs);
+    (void)hipFree(b->d_tasks);
+    (void)hipFree(b->d_counter);
+    (void)hipFree(b->d_jobs_g);
+    (void)hipFree(b->d_tasks_g);
+    (void)hipFree(b->d_counter_g);
+    (void)hipFree(b->d_scratch);
+    if (b->h_jobs) (void)hipHostFree(b->h_jobs);
+    if (b->h_tasks) (void)hipHostFree(b->h_tasks);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+    return STIXELS_OK;
+}
+
+int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, void* stream) {
+    if (!b) return STIXELS_E_INVALID_ARG;
+    int slots = 0, ntasks = 0, grid = 0;
+    long long stride = 0;
+    int rc = stage(b, jobs, n, &slots, &ntasks, &stride);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
+    if (rc != STIXELS_OK) return rc;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
+    if (rc != STIXELS_OK) return rc;
+    const hipError_t e = launch_batch(slots, grid, st, b->d_jobs, b->d_tasks, ntasks,
+                                      b->d_counter, b->d_scratch, stride);
+    if (e != hipSuccess)
+        return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
+    b->last_grid = grid;
+    b->last_tasks = ntasks;
+    return STIXELS_OK;
+}
+
+int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, void* stream) {
+    if (!b) return STIXELS_E_INVALID_ARG;
+    if (!stream)
+        return bfail(b, STIXELS_E_INVALID_ARG, "the null stream cannot be captured; pass a created stream");
+    int slots = 0, ntasks = 0, grid = 0;
+    long long stride = 0;
+    int rc = stage(b, jobs, n, &slots, &ntasks, &stride);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
+    if (rc != STIXELS_OK) return rc;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    // the graph reads its own descriptor copy, uploaded once here
+    rc = upload(b, b->d_jobs_g, b->d_tasks_g, n, ntasks, st);
+    if (rc != STIXELS_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return bfail(b, STIXELS_E_HIP, "synchronising the capture stream failed");
+    b->staged_pending = false;
+    destroy_graph(b);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
+    const hipError_t e = launch_batch(slots, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+                                      b->d_counter_g, b->d_scratch, stride);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess || e2 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, STIXELS_E_HIP, "capturing the batch launch failed");
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        destroy_graph(b);
+        return bfail(b, STIXELS_E_HIP, "hipGraphInstantiate failed");
+    }
+    b->last_grid = grid;
+    b->last_tasks = ntasks;
+    return STIXELS_OK;
+}
+
+int stixels_batch_replay(stixels_batch* b, void* stream) {
+    if (!b) return STIXELS_E_INVALID_ARG;
+    if (!b->exec) return bfail(b, STIXELS_E_INVALID_ARG, "no captured batch to replay");
+    if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return bfail(b, STIXELS_E_HIP, "hipGraphLaunch failed");
+    return STIXELS_OK;
+}
+
+int stixels_batch_info(const stixels_batch* b, int32_t* workgroups, int32_t* tasks) {
+    if (!b) return STIXELS_E_INVALID_ARG;
+    if (workgroups) *workgroups = b->last_grid;
+    if (tasks) *tasks = b->last_tasks;
+    return STIXELS_OK;
+}
+
+const char* stixels_batch_last_error(const stixels_batch* b) {
+    return b ? b->err.c_str() : "";
+}
+
+}  // extern "C"

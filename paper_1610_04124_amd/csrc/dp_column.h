@@ -1,0 +1,299 @@
+// dp_column.h -- the Eq. 5-6 recurrence and backtracking for one column, run
+// by one wave64.
+//
+// Work distribution (gfx950): lane l owns the rows k = 64*s + l for slots
+// s < S, with its running minima OB^k, GR^k, SK^k, the mean of the best
+// object stixel ending at k, and the prefix values at k+1 held in VGPRs.  The
+// recurrence is evaluated in push form: once row j is final (all candidates
+// with a cut at b <= j have been seen), its costs are broadcast from the
+// owning lane with v_readlane and every lane folds the candidates that start
+// at b = j+1 into its rows k > j.  There is no barrier, no LDS and no
+// cross-lane reduction per step, unlike the one-thread-per-k CTA of Sec. 4.3.
+//
+// The index table of Sec. 3.3 is not stored.  Because every cost is exact on
+// the grid, backtracking recovers each link by recomputing the candidates of
+// a row and taking the first one equal to the row's minimum, in the order of
+// Eq. 6: the bottom-stixel candidate, then cut positions b ascending, then
+// predecessor classes object, ground, sky.  This is the same choice as a
+// first-minimum index table.
+#pragma once
+
+#include "internal.h"
+
+namespace stx {
+
+struct ColumnIn {
+    const float* PG;        // [H+1] ground cost prefix
+    const float* PS;        // [H+1] sky cost prefix
+    const float* PA;        // [H+1] prefix of 2*q+1 over valid pixels
+    const float* PN2;       // [H+1] prefix of 2 over valid pixels
+    const float* PO;        // [fmax-fmin+1][H+1] object cost prefix, row f-fmin
+    int fmin, fmax;
+    const int32_t* fg_hi;   // diving threshold per top-down image row
+    const int32_t* fg_lo;   // gravity threshold per top-down image row
+};
+
+struct ColumnOut {
+    int32_t* count;
+    uint32_t* rec;          // capacity records of 3 dwords (stixels_record)
+    float* total;
+    uint8_t* overflow;
+    int cap;
+};
+
+template <int S>
+__device__ __forceinline__ float sel_slot(const float (&a)[S], int k) {
+    float v = 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if ((k >> 6) == s) v = readlane_f(a[s], k & 63);
+    return v;
+}
+
+// Emitted stixel, kept by lane t (t-th stixel found from the top).
+struct RecRegs {
+    uint32_t w0, w1;
+    float w2;
+};
+
+__device__ __forceinline__ void pack_record(int vb, int vt, int cls, int f, float cost,
+                                            uint32_t& w0, uint32_t& w1, float& w2) {
+    w0 = (uint32_t)(vb & 0xffff) | ((uint32_t)(vt & 0xffff) << 16);
+    w1 = (uint32_t)(cls & 0xff) | ((uint32_t)(f & 0xff) << 8);
+    w2 = cost;
+}
+
+// a[c] for a class index known only at run time, without indexable memory
+__device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
+    return c == 0 ? a0 : (c == 1 ? a1 : a2);
+}
+
+template <int S>
+__device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
+                             const ColumnOut& out) {
+    const int lane = threadIdx.x & 63;
+    const int stride = H + 1;
+    const int fmin = in.fmin, fmax = in.fmax;
+    const uint32_t po_bytes = (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u;
+    const auto po = make_rsrc(in.PO, po_bytes);
+    const float eps = P.mean_eps;
+    const float INF = inf_f();
+
+    float eG[S], eS[S], eA[S], eN[S];   // prefix values at k+1 (ground masked above vtop)
+    float mO[S], mG[S], mS[S];          // OB^k, GR^k, SK^k so far
+    int fO[S];                          // mean of the best object stixel ending at k
+
+    // Slots past the column's height (a shorter frame in a batch sized for
+    // taller ones) are skipped with wave-uniform branches.
+    const int nslots = (H + 63) >> 6;
+
+    // Bottom-stixel candidates (b = 0): data(0, k) + F[c] + beta.
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (s >= nslots) {
+            eG[s] = eS[s] = mO[s] = mG[s] = mS[s] = INF;
+            eA[s] = eN[s] = 0.0f;
+            fO[s] = 0;
+            continue;
+        }
+        const int k = s * 64 + lane;
+        const int kk = min(k + 1, H);
+        const float pg = in.PG[kk], ps = in.PS[kk];
+        eG[s] = (k < H && k <= vtop) ? pg : INF;
+        eS[s] = (k < H) ? ps : INF;
+        eA[s] = in.PA[kk];
+        eN[s] = in.PN2[kk];
+        const int f = rounded_mean(eA[s], eN[s], eps);
+        const int fi = min(max(f, fmin), fmax) - fmin;
+        mO[s] = buf_load(po, fi * stride + kk) + P.first[0];
+        fO[s] = f;
+        mG[s] = eG[s] + P.first[1];
+        mS[s] = eS[s] + P.first[2];
+    }
+
+    // Push-form recurrence: step j finalises row j and folds cut b = j+1.
+#pragma unroll
+    for (int sj = 0; sj < S; ++sj) {
+        const int jend = min(64, H - 1 - sj * 64);
+        for (int jl = 0; jl < jend; ++jl) {
+            const int b = sj * 64 + jl + 1;
+            const float Co = readlane_f(mO[sj], jl);
+            const float Cg = readlane_f(mG[sj], jl);
+            const float Cs = readlane_f(mS[sj], jl);
+            const int fp = readlane_i(fO[sj], jl);
+            const float bG = readlane_f(eG[sj], jl);
+            const float bS = readlane_f(eS[sj], jl);
+            const float bA = readlane_f(eA[sj], jl);
+            const float bN = readlane_f(eN[sj], jl);
+            const int r = H - 1 - b;                 // top-down row of the stixel base
+            const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
+            // predecessor terms shared by all rows k >= b
+            const float XG = (b <= vtop)
+                ? fminf(fminf(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
+                : INF;
+            const float XS =
+                fminf(fminf(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+            const float Xoo = Co + P.trans[0][0];
+            const float Xoo_p = Xoo + P.c_ord;
+            const int tord = fp + P.tau_ord;
+            const float Xgo = Cg + P.trans[1][0];
+            const float Xgo_d = Xgo + P.c_dive;
+            const float Xgo_g = Xgo + P.c_grav;
+            const float Xso = Cs + P.trans[2][0];
+#pragma unroll
+            for (int s = sj; s < S; ++s) {
+                if (s >= nslots) break;
+                if (s > sj || lane > jl) {
+                    mG[s] = fminf(mG[s], eG[s] + XG);
+                    mS[s] = fminf(mS[s], eS[s] + XS);
+                    const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
+                    const int fi = min(max(f, fmin), fmax) - fmin;
+                    const int kk = min(s * 64 + lane + 1, H);
+                    const float d = buf_load(po, fi * stride + kk) - buf_load(po, fi * stride + b);
+                    const float v1 = (f > tord) ? Xoo_p : Xoo;
+                    float v2 = (f < tlo) ? Xgo_g : Xgo;
+                    v2 = (f > thi) ? Xgo_d : v2;
+                    const float c = fminf(fminf(v1, v2), Xso) + d;
+                    if (c < mO[s]) {
+                        mO[s] = c;
+                        fO[s] = f;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---------------------------------------------------------- backtracking
+    const int ktop = H - 1;
+    float total = sel_slot<S>(mO, ktop);
+    int ctop = 0;
+    {
+        const float g = sel_slot<S>(mG, ktop), sk = sel_slot<S>(mS, ktop);
+        if (g < total) { total = g; ctop = 1; }
+        if (sk < total) { total = sk; ctop = 2; }
+    }
+
+    // Walk the links from the top.  direct = false keeps the first 64
+    // stixels in lane registers (stixel t in lane t) and only counts the
+    // rest; direct = true writes every stixel straight to its bottom-up
+    // position (second pass, needed only for more than 64 stixels).
+    auto walk = [&](bool direct, int n_total, RecRegs& rr) -> int {
+        int k = ktop, cls = ctop, t = 0;
+        float target = total;
+        while (true) {
+            const float kG = sel_slot<S>(eG, k), kS = sel_slot<S>(eS, k);
+            const float kA = sel_slot<S>(eA, k), kN = sel_slot<S>(eN, k);
+            const int kk = k + 1;
+            int lb = -1, lc = -1, lf = 0;
+            float prevC = 0.0f;
+            // priors of the three predecessor classes into class cls
+            const float tO = pick3(P.trans[0][0], P.trans[0][1], P.trans[0][2], cls);
+            const float tG = pick3(P.trans[1][0], P.trans[1][1], P.trans[1][2], cls);
+            const float tS = pick3(P.trans[2][0], P.trans[2][1], P.trans[2][2], cls);
+            {   // bottom stixel b = 0 (prefix entries at 0 are zero)
+                int f0 = 0;
+                float d0;
+                if (cls == 0) {
+                    f0 = rounded_mean(kA, kN, eps);
+                    const int fi = min(max(f0, fmin), fmax) - fmin;
+                    d0 = buf_load(po, fi * stride + kk);
+                } else {
+                    d0 = (cls == 1) ? kG : kS;
+                }
+                if (d0 + pick3(P.first[0], P.first[1], P.first[2], cls) == target) {
+                    lb = 0;
+                    lf = f0;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (lb < 0 && s * 64 < k) {
+                    const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
+                    const bool inr = p < k;
+                    const int bb = p + 1;
+                    float data;
+                    int f = 0;
+                    float pen_o = 0.0f, pen_g = 0.0f;
+                    if (cls == 0) {
+                        f = rounded_mean(kA - eA[s], kN - eN[s], eps);
+                        const int fi = min(max(f, fmin), fmax) - fmin;
+                        data = buf_load(po, fi * stride + kk) - buf_load(po, fi * stride + bb);
+                        pen_o = (f > fO[s] + P.tau_ord) ? P.c_ord : 0.0f;
+                        const int r = inr ? H - 1 - bb : 0;
+                        const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
+                        pen_g = (f > thi) ? P.c_dive : ((f < tlo) ? P.c_grav : 0.0f);
+                    } else if (cls == 1) {
+                        data = kG - eG[s];
+                    } else {
+                        data = kS - eS[s];
+                    }
+                    const float co = mO[s] + tO + pen_o + data;
+                    const float cg = mG[s] + tG + pen_g + data;
+                    const float cs = mS[s] + tS + data;
+                    const int code = !inr ? 3
+                                   : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
+                    const uint64_t m = __ballot(code < 3);
+                    if (m) {
+                        const int l0 = (int)__builtin_ctzll(m);
+                        lb = s * 64 + l0 + 1;
+                        lc = readlane_i(code, l0);
+                        lf = readlane_i(f, l0);
+                        const float pc = (lc == 0) ? mO[s] : ((lc == 1) ? mG[s] : mS[s]);
+                        prevC = readlane_f(pc, l0);
+                    }
+                }
+            }
+            if (lb < 0) return -1;
+            const float cost = (lb > 0) ? target - prevC : target;
+            const int fout = (cls == 0) ? lf : 0;
+            if (!direct) {
+                if (lane == t) pack_record(lb, k, cls, fout, cost, rr.w0, rr.w1, rr.w2);
+            } else {
+                const int pos = n_total - 1 - t;
+                if (pos < out.cap && lane == 0) {
+                    uint32_t w0, w1;
+                    float w2;
+                    pack_record(lb, k, cls, fout, cost, w0, w1, w2);
+                    out.rec[pos * 3 + 0] = w0;
+                    out.rec[pos * 3 + 1] = w1;
+                    out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, w2);
+                }
+            }
+            ++t;
+            if (lb == 0) break;
+            k = lb - 1;
+            cls = lc;
+            target = prevC;
+        }
+        return t;
+    };
+
+    RecRegs rr{0u, 0u, 0.0f};
+    const int n = walk(false, 0, rr);
+    if (n < 0) {
+        if (lane == 0) {
+            *out.count = 0;
+            *out.total = total;
+            *out.overflow = 255;
+        }
+        return;
+    }
+    if (n <= 64) {
+        const int pos = n - 1 - lane;
+        if (lane < n && pos < out.cap) {
+            out.rec[pos * 3 + 0] = rr.w0;
+            out.rec[pos * 3 + 1] = rr.w1;
+            out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, rr.w2);
+        }
+    } else {
+        RecRegs dummy{0u, 0u, 0.0f};
+        walk(true, n, dummy);
+    }
+    if (lane == 0) {
+        *out.count = n < out.cap ? n : out.cap;
+        *out.total = total;
+        *out.overflow = (uint8_t)(n > out.cap ? 1 : 0);
+    }
+}
+
+}  // namespace stx

@@ -1,0 +1,299 @@
+// frame_kernels.hip -- the per-frame pipeline of Sec. 4 as three gfx950 kernels:
+//   reduce  (Sec. 4.1)  s-pixel strips -> one reduced disparity, transposed to
+//                       bottom-up columns through an LDS tile so that both the
+//                       row-major reads and the column-major writes coalesce;
+//   tables  (Sec. 4.2)  per column: ground / sky / disparity / count prefix
+//                       sums and the object prefix table over the column's
+//                       own disparity range, with DPP wave scans;
+//   dp      (Sec. 4.3-4.4)  the recurrence and backtracking, one wave64 per
+//                       column (dp_column.h).
+#include <climits>
+
+#include "dp_column.h"
+#include "launch.h"
+
+namespace stx {
+
+// ------------------------------------------------------------------ reduce
+// One workgroup reduces a tile of 64 columns x 64 image rows.
+template <int S>
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ disp, int W, int H,
+                                                     int ncols, int D, int mode,
+                                                     int16_t* __restrict__ q) {
+    __shared__ int16_t tile[64][65];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int col = c0 + tx;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        const int rl = ty + 4 * i;
+        const int r = r0 + rl;
+        int v = -1;
+        if (col < ncols && r < H)
+            v = reduce_strip<S>(disp + (size_t)r * W + (size_t)col * S, mode, D);
+        tile[tx][rl] = (int16_t)v;
+    }
+    __syncthreads();
+    // tile row rl (image row r0+rl) lands at bottom-up row H-1-r: write each
+    // column's 64 rows as one contiguous run of ascending v
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        const int cl = e >> 6, vl = e & 63;
+        const int rl = 63 - vl;
+        const int r = r0 + rl;
+        const int cg = c0 + cl;
+        if (cg < ncols && r < H) q[(size_t)cg * H + (H - 1 - r)] = tile[cl][rl];
+    }
+}
+
+// ------------------------------------------------------------------ tables
+struct TablesArgs {
+    const int16_t* q;
+    float* prefix;
+    int32_t* range;
+    float* po;
+    const float* sky;
+    const float* ground;
+    const float* object_t;
+    int H, ncols, D;
+};
+
+__global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
+    __shared__ int16_t qs[kMaxHeight];
+    __shared__ int smin, smax;
+    const int col = blockIdx.x;
+    const int H = a.H, D = a.D, ncols = a.ncols;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        smin = INT_MAX;
+        smax = -1;
+    }
+    __syncthreads();
+    int lmin = INT_MAX, lmax = -1;
+    for (int v = tid; v < H; v += 256) {
+        const int x = a.q[(size_t)col * H + v];
+        qs[v] = (int16_t)x;
+        if (x >= 0) {
+            lmin = min(lmin, x);
+            lmax = max(lmax, x);
+        }
+    }
+    atomicMin(&smin, lmin);
+    atomicMax(&smax, lmax);
+    __syncthreads();
+    int fmin = smin, fmax = smax;
+    if (fmax < 0) {
+        fmin = 0;
+        fmax = 0;
+    }
+    const int stride = H + 1;
+
+    if (wave == 0) {
+        float* PG = a.prefix + ((size_t)0 * ncols + col) * stride;
+        float* PS = a.prefix + ((size_t)1 * ncols + col) * stride;
+        float* PA = a.prefix + ((size_t)2 * ncols + col) * stride;
+        float* PN = a.prefix + ((size_t)3 * ncols + col) * stride;
+        if (lane == 0) {
+            PG[0] = 0.0f;
+            PS[0] = 0.0f;
+            PA[0] = 0.0f;
+            PN[0] = 0.0f;
+            a.range[2 * col] = fmin;
+            a.range[2 * col + 1] = fmax;
+        }
+        float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+        for (int base = 0; base < H; base += 64) {
+            const int v = base + lane;
+            const int x = (v < H) ? (int)qs[v] : -1;
+            float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+            if (x >= 0) {
+                g = a.ground[(size_t)(H - 1 - v) * D + x];
+                sk = a.sky[x];
+                aa = (float)(2 * x + 1);
+                nn = 2.0f;
+            }
+            g = wave_inclusive_scan(g) + cg;
+            sk = wave_inclusive_scan(sk) + cs;
+            aa = wave_inclusive_scan(aa) + ca;
+            nn = wave_inclusive_scan(nn) + cn;
+            if (v < H) {
+                PG[v + 1] = g;
+                PS[v + 1] = sk;
+                PA[v + 1] = aa;
+                PN[v + 1] = nn;
+            }
+            cg = readlane_f(g, 63);
+            cs = readlane_f(sk, 63);
+            ca = readlane_f(aa, 63);
+            cn = readlane_f(nn, 63);
+        }
+    }
+
+    float* PO = a.po + (size_t)col * D * stride;
+    for (int f = fmin + wave; f <= fmax; f += 4) {
+        const float* orow = a.object_t + (size_t)f * D;
+        float* prow = PO + (size_t)(f - fmin) * stride;
+        if (lane == 0) prow[0] = 0.0f;
+        float carry = 0.0f;
+        for (int base = 0; base < H; base += 64) {
+            const int v = base + lane;
+            const int x = (v < H) ? (int)qs[v] : -1;
+            float o = (x >= 0) ? orow[x] : 0.0f;
+            o = wave_inclusive_scan(o) + carry;
+            if (v < H) prow[v + 1] = o;
+            carry = readlane_f(o, 63);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dp
+struct DpArgs {
+    const float* prefix;
+    const int32_t* range;
+    const float* po;
+    const int32_t* fg_hi;
+    const int32_t* fg_lo;
+    int32_t* counts;
+    uint32_t* records;
+    float* total;
+    uint8_t* overflow;
+    int cap, H, ncols, D, vtop;
+    Prior prior;
+};
+
+template <int S>
+__global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
+    const int col = blockIdx.x;
+    const int stride = a.H + 1;
+    ColumnIn in;
+    in.PG = a.prefix + ((size_t)0 * a.ncols + col) * stride;
+    in.PS = a.prefix + ((size_t)1 * a.ncols + col) * stride;
+    in.PA = a.prefix + ((size_t)2 * a.ncols + col) * stride;
+    in.PN2 = a.prefix + ((size_t)3 * a.ncols + col) * stride;
+    in.PO = a.po + (size_t)col * a.D * stride;
+    in.fmin = a.range[2 * col];
+    in.fmax = a.range[2 * col + 1];
+    in.fg_hi = a.fg_hi;
+    in.fg_lo = a.fg_lo;
+    ColumnOut out;
+    out.count = a.counts + col;
+    out.rec = a.records + (size_t)col * a.cap * 3;
+    out.total = a.total + col;
+    out.overflow = a.overflow + col;
+    out.cap = a.cap;
+    solve_column<S>(a.H, a.vtop, a.prior, in, out);
+}
+
+// ------------------------------------------------------------------ self-test
+__global__ __launch_bounds__(256) void selftest_mean_kernel(int D, float eps,
+                                                            unsigned long long* bad) {
+    const int n = blockIdx.x + 1;
+    const long long smax = (long long)n * (D - 1);
+    unsigned long long local = 0;
+    for (long long S = threadIdx.x; S <= smax; S += 256) {
+        const int a = (int)(2 * S + n);
+        const int want = a / (2 * n);
+        const int got = rounded_mean((float)a, (float)(2 * n), eps);
+        local += (got != want) ? 1ull : 0ull;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+// ------------------------------------------------------------------ launchers
+int ground_top(double horizon_row, int H) {
+    const double vh = floor((double)(H - 1) - horizon_row);
+    if (vh < -1.0) return -1;
+    if (vh > (double)H) return H;
+    return (int)vh;
+}
+
+template <int S>
+static void reduce_launch(dim3 g, const DeviceModel& m, const float* disp, int W, int H, int ncols,
+                          int16_t* q, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_kernel<S>, g, dim3(256), 0, st, disp, W, H, ncols, m.D,
+                       m.reduce_mode, q);
+}
+
+hipError_t launch_reduce(const DeviceModel& m, const float* disp, int W, int H, int ncols,
+                         int16_t* q, hipStream_t st) {
+    const dim3 g((ncols + 63) / 64, (H + 63) / 64);
+    switch (m.s) {
+#define STX_CASE(n) case n: reduce_launch<n>(g, m, disp, W, H, ncols, q, st); break;
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols,
+                         int vtop, hipStream_t st) {
+    (void)vtop;
+    TablesArgs a;
+    a.q = ws.q;
+    a.prefix = ws.prefix;
+    a.range = ws.range;
+    a.po = ws.po;
+    a.sky = m.sky;
+    a.ground = m.ground;
+    a.object_t = m.object_t;
+    a.H = H;
+    a.ncols = ncols;
+    a.D = m.D;
+    hipLaunchKernelGGL(tables_kernel, dim3(ncols), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
+                     const FrameOutput& out, hipStream_t st) {
+    DpArgs a;
+    a.prefix = ws.prefix;
+    a.range = ws.range;
+    a.po = ws.po;
+    a.fg_hi = m.fg_hi;
+    a.fg_lo = m.fg_lo;
+    a.counts = out.counts;
+    a.records = out.records;
+    a.total = out.total;
+    a.overflow = out.overflow;
+    a.cap = out.cap;
+    a.H = H;
+    a.ncols = ncols;
+    a.D = m.D;
+    a.vtop = vtop;
+    a.prior = m.prior;
+    const int slots = (H + 63) / 64;
+    const dim3 g(ncols), b(64);
+    switch (slots) {
+#define STX_CASE(n) case n: hipLaunchKernelGGL(dp_kernel<n>, g, b, 0, st, a); break;
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_selftest_mean(int D, int max_height, int64_t* mismatches) {
+    unsigned long long* d_bad = nullptr;
+    hipError_t e = hipMalloc(&d_bad, sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    e = hipMemset(d_bad, 0, sizeof(unsigned long long));
+    if (e == hipSuccess) {
+        const float eps = (float)ldexp((double)D, -22);
+        hipLaunchKernelGGL(selftest_mean_kernel, dim3(max_height), dim3(256), 0, nullptr, D, eps,
+                           d_bad);
+        e = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (e == hipSuccess) e = hipMemcpy(&h, d_bad, sizeof(h), hipMemcpyDeviceToHost);
+    (void)hipFree(d_bad);
+    *mismatches = (int64_t)h;
+    return e;
+}
+
+}  // namespace stx

@@ -1,0 +1,38 @@
+// handle.h -- layout of a stixel handle (one camera model), shared by the
+// per-frame entry points and the batched launch.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "stixels.h"
+
+struct stixels_handle {
+    stixels_params p;
+    int D = 0, Hmax = 0, Wmax = 0, s = 0, ncols_max = 0;
+    int device = 0;
+    // host copies of the rounded tables
+    std::vector<float> sky, ground, object_t;
+    std::vector<int32_t> fg_hi, fg_lo;
+    // device tables
+    float* d_sky = nullptr;
+    float* d_ground = nullptr;
+    float* d_object_t = nullptr;
+    int32_t* d_fg_hi = nullptr;
+    int32_t* d_fg_lo = nullptr;
+    // per-frame workspace
+    int16_t* d_q = nullptr;
+    float* d_prefix = nullptr;
+    int32_t* d_range = nullptr;
+    float* d_po = nullptr;
+    stx::Prior prior{};
+    std::string err;
+    int last_W = 0, last_H = 0;
+};
+
+// Device view of a handle's resident tables and priors.
+inline stx::DeviceModel device_model(const stixels_handle* h) {
+    return stx::DeviceModel{h->d_sky, h->d_ground, h->d_object_t, h->d_fg_hi, h->d_fg_lo, h->D,
+                            h->Hmax, h->p.reduce_mode, h->s, h->p.camera.horizon_row, h->prior};
+}

@@ -1,0 +1,138 @@
+// internal.h -- device building blocks of the gfx950 stixel library.
+//
+// Layout in HBM (per frame, per reduced column i of height h):
+//   q      int16 [ncols][h]            reduced disparities, bottom-up, -1 invalid
+//   prefix float [4][ncols][h+1]       PG (ground), PS (sky), PA = 2*sum(q)+count,
+//                                      PN2 = 2*count; entry v+1 covers rows 0..v
+//   range  int32 [ncols][2]            smallest / largest valid q of the column
+//   PO     float [ncols][D][h+1]       object prefix table, row f-fmin holds
+//                                      sum over rows of O[q_v][f]
+// Every cost value is a multiple of 2^-g and every partial sum stays below
+// 2^(24-g) in magnitude (checked when a handle is created), so FP32 adds,
+// subtractions and minima are exact and their order does not matter.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "stixels.h"
+
+namespace stx {
+
+constexpr int kWave = 64;
+constexpr int kMaxSlots = 16;          // rows per lane in the recurrence: h <= 1024
+constexpr int kMaxHeight = kWave * kMaxSlots;
+constexpr int kMaxStixelWidth = 16;
+constexpr int kMaxDisparity = 256;
+constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
+
+// Quantised prior constants of one camera model, in FP32 (exact on the grid).
+struct Prior {
+    float first[3];       // F[c] + beta
+    float trans[3][3];    // T[prev][cur] + beta (INFINITY when forbidden)
+    float c_ord, c_grav, c_dive;
+    int tau_ord;
+    float mean_eps;       // bias of the rounded-mean division, d_range * 2^-22
+};
+
+// Per-frame geometry shared by the kernels.
+struct FrameGeom {
+    int W, H, s, ncols, D;
+    int vtop;             // highest bottom-up row a ground stixel may reach
+    int reduce_mode;
+};
+
+__device__ __forceinline__ float inf_f() { return __builtin_inff(); }
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ int readlane_i(int v, int lane) {
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+// ------------------------------------------------------------------ Sec. 4.1
+// One reduced pixel from the s disparities of a row strip: lower median (mode
+// 0) or FP64 mean (mode 1) of the valid values, rounded half to even and
+// clamped to d_range-1; -1 when no value is valid.  The median is an exact
+// rank selection: the value whose rank (ties broken by position) is (n-1)/2.
+template <int S>
+__device__ __forceinline__ int reduce_strip(const float* __restrict__ p, int mode, int D) {
+    float x[S];
+    bool ok[S];
+    int n = 0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        x[t] = p[t];
+        ok[t] = (x[t] >= 0.0f) && (x[t] <= 3.402823466e38f);
+        n += ok[t] ? 1 : 0;
+    }
+    if (n == 0) return -1;
+    if (mode == 0) {
+        const int want = (n - 1) >> 1;
+        float med = 0.0f;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            int rank = 0;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const bool before = (x[j] < x[i]) || (x[j] == x[i] && j < i);
+                rank += (ok[j] && before) ? 1 : 0;
+            }
+            if (ok[i] && rank == want) med = x[i];
+        }
+        const float r = __builtin_rintf(med);
+        const float top = (float)(D - 1);
+        return (int)(r < top ? r : top);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+        if (ok[t]) sum += (double)x[t];
+    const double r = __builtin_rint(sum / (double)n);
+    const double top = (double)(D - 1);
+    return (int)(r < top ? r : top);
+}
+
+// ------------------------------------------------------------------ scans
+// Inclusive prefix sum over the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (exact: every addend is on the cost grid or an integer).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_shift(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x),
+                                                                 CTRL, ROWMASK, 0xf, true));
+}
+
+__device__ __forceinline__ float wave_inclusive_scan(float x) {
+    x += dpp_shift<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_shift<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_shift<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_shift<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_shift<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_shift<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// ------------------------------------------------------------------ Sec. 3.4
+// Rounded mean of a stixel's valid disparities, floor((2S+n)/(2n)), from the
+// prefix differences a = 2S+n and n2 = 2n (both exact integers in FP32).
+// With r = rcp(n2) (relative error <= 2^-23) and eps = d_range * 2^-22,
+// fma(a, r, eps) lies in [m, m+1) for a/n2 in [m, m+1) whenever
+// 2n * d_range < 2^24 / 7, which handle creation enforces.  n = 0 gives 0.
+__device__ __forceinline__ int rounded_mean(float a, float n2, float eps) {
+    const float r = __builtin_amdgcn_rcpf(fmaxf(n2, 1.0f));
+    return (int)floorf(__builtin_fmaf(a, r, eps));
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             (int)kBufferWord3);
+}
+
+// Load element `idx` (float) through a bounds-checked buffer resource: an
+// index past the resource's size reads 0 instead of faulting.
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int idx) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+
+}  // namespace stx

@@ -1,0 +1,57 @@
+"""Shared helpers of the GPU parity tests (not collected by pytest)."""
+
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+import paper_1610_04124_amd as P
+
+
+def announce(msg: str) -> None:
+    """Name the case on the real stderr before a GPU step (survives capture)."""
+    sys.__stderr__.write(f"[gpu-case] {msg}\n")
+    sys.__stderr__.flush()
+
+
+def device():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test run without a visible ROCm device")
+    return torch.device("cuda", 0)
+
+
+def to_device(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device())
+
+
+def gpu_frame(handle: P.Stixels, disp: np.ndarray, capacity: int | None = None) -> dict:
+    import torch
+    H, W = disp.shape
+    cap = capacity if capacity else handle.capacity(H)
+    out = P.FrameOutput(handle.num_columns(W), cap, device())
+    handle.compute(to_device(disp), out)
+    torch.cuda.synchronize()
+    return out.to_host()
+
+
+def assert_frames_equal(gpu: dict, ref: dict, label: str = "") -> None:
+    """Bit-exact parity of a frame: counts, overflow flags, every record's
+    boundaries, class, disparity and cost, and the column totals.  Costs are
+    exact on the cost grid, so the FP32 values equal the FP64 oracle's."""
+    ncols = len(ref["counts"])
+    assert len(gpu["counts"]) == ncols, label
+    bad = np.nonzero((gpu["counts"] != ref["counts"]) | (gpu["overflow"] != ref["overflow"])
+                     | (gpu["total"].astype(np.float64) != ref["total"]))[0]
+    assert bad.size == 0, (f"{label}: column {bad[0]} count {gpu['counts'][bad[0]]} vs "
+                           f"{ref['counts'][bad[0]]}, total {gpu['total'][bad[0]]} vs "
+                           f"{ref['total'][bad[0]]}, overflow {gpu['overflow'][bad[0]]}")
+    for i in range(ncols):
+        n = int(ref["counts"][i])
+        g, r = gpu["records"][i, :n], ref["records"][i, :n]
+        for f in ("v_bottom", "v_top", "cls", "disparity"):
+            assert np.array_equal(g[f], r[f]), (label, i, f, g, r)
+        assert np.array_equal(g["cost"].astype(np.float64), r["cost"]), (label, i, g, r)

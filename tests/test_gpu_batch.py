@@ -1,0 +1,125 @@
+"""GPU parity of the persistent batched launch: against the oracle, against
+the per-frame path (bitwise), across uneven frame sizes / stixel widths /
+cameras, across workgroup counts, and through HIP graph replays."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1610_04124_amd as P
+from gpu_helpers import announce, assert_frames_equal, device, gpu_frame, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def frame_setup(n, seeds=None):
+    p = synth.make_params()
+    h = P.Stixels(p)
+    seeds = seeds if seeds is not None else list(range(n))
+    frames = [synth.generate_frame(synth.SceneSpec(seed=s)) for s in seeds]
+    return p, h, frames
+
+
+def run_batch(items, workgroups=0, max_h=440, max_d=128):
+    import torch
+    b = P.Batch(len(items), sum(h.num_columns(d.shape[1]) for h, d, _ in items), max_h, max_d,
+                workgroups)
+    b.compute(items)
+    torch.cuda.synchronize()
+    return b
+
+
+def test_batch64_matches_oracle_and_per_frame():
+    """64 frames of 1024x440, stixel width 5 (the batched headline workload)."""
+    import torch
+    announce("batch 64 x 1024x440")
+    p, h, frames = frame_setup(64)
+    dev = device()
+    outs = [h.new_output(1024, 440) for _ in frames]
+    items = [(h, to_device(f), o) for f, o in zip(frames, outs)]
+    b = run_batch(items)
+    g, t = b.info()
+    assert t == 64 * 204 and g >= 1
+    for i in (0, 17, 63):
+        assert_frames_equal(outs[i].to_host(), oracle.frame(p, frames[i]), f"batch frame {i}")
+    for i, f in enumerate(frames):
+        assert_frames_equal(outs[i].to_host(), gpu_frame(h, f), f"batch vs per-frame {i}")
+
+
+def uneven_items(n):
+    """Frames of the uneven workload: four sizes, stixel widths 3/5/7, their
+    own cameras and disparity ranges, one handle per frame."""
+    items, refs = [], []
+    for i in range(n):
+        disp, info = synth.workload_frame("uneven256", i)
+        W, H = info["width"], info["height"]
+        p = synth.make_params(camera=info["camera"], stixel_width=info["stixel_width"],
+                              max_disparity=info["d_max"], max_width=W, max_height=H)
+        h = P.Stixels(p)
+        items.append((h, to_device(disp), h.new_output(W, H)))
+        refs.append((p, disp))
+    return items, refs
+
+
+@pytest.mark.parametrize("workgroups", [0, 7])
+def test_uneven_batch_matches_oracle(workgroups):
+    announce(f"uneven batch workgroups={workgroups}")
+    items, refs = uneven_items(10)
+    run_batch(items, workgroups, max_h=880, max_d=256)
+    for i, ((h, d, out), (p, disp)) in enumerate(zip(items, refs)):
+        assert_frames_equal(out.to_host(), oracle.frame(p, disp), f"uneven frame {i}")
+
+
+def test_graph_replays_are_stable_and_follow_inputs():
+    """Capture once, replay several times with eager work and syncs between
+    the replays; each replay equals the per-frame result of the inputs it
+    saw, including after the inputs are rewritten in place."""
+    import torch
+    announce("graph replay")
+    p, h, frames = frame_setup(8)
+    dev_frames = [to_device(f) for f in frames]
+    outs = [h.new_output(1024, 440) for _ in frames]
+    items = list(zip([h] * 8, dev_frames, outs))
+    b = P.Batch(8, 8 * 204, 440, 128)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b.capture(items, stream)
+    expect = [gpu_frame(h, f) for f in frames]
+    for rep in range(3):
+        for o in outs:
+            o.counts.fill_(-1)
+        torch.cuda.synchronize()
+        b.replay(stream)
+        torch.cuda.synchronize()
+        _ = torch.ones(1024, device=dev_frames[0].device).sum().item()   # eager work between replays
+        for i in range(8):
+            assert_frames_equal(outs[i].to_host(), expect[i], f"replay {rep} frame {i}")
+    # rewrite the inputs in place: the graph reads the same buffers
+    new = [synth.generate_frame(synth.SceneSpec(seed=100 + i)) for i in range(8)]
+    for df, nf in zip(dev_frames, new):
+        df.copy_(torch.from_numpy(nf))
+    torch.cuda.synchronize()
+    b.replay(stream)
+    torch.cuda.synchronize()
+    for i in range(8):
+        assert_frames_equal(outs[i].to_host(), gpu_frame(h, new[i]), f"new input frame {i}")
+
+
+def test_batch_limits_are_enforced():
+    announce("batch limits")
+    p, h, frames = frame_setup(3)
+    items = [(h, to_device(f), h.new_output(1024, 440)) for f in frames]
+    b = P.Batch(2, 10000, 440, 128)
+    with pytest.raises(P.StixelsError):
+        b.compute(items)                      # more jobs than max_jobs
+    b = P.Batch(3, 300, 440, 128)
+    with pytest.raises(P.StixelsError):
+        b.compute(items)                      # more columns than max_tasks
+    b = P.Batch(3, 1000, 400, 128)
+    with pytest.raises(P.StixelsError):
+        b.compute(items)                      # taller than the batch's max_height
+    with pytest.raises(P.StixelsError):
+        P.Batch(1, 1, 440, 128).replay()      # nothing captured
+    with pytest.raises(P.StixelsError):
+        b.capture(items[:1], None)            # the null stream cannot be captured
