@@ -65,13 +65,15 @@ __device__ __forceinline__ int wave_max_i(int x) {
 __global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
 
 template <int S>
-__global__ __launch_bounds__(64) void batch_kernel(const JobDesc* __restrict__ jobs,
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const JobDesc* __restrict__ jobs,
                                                    const int2* __restrict__ tasks, int ntasks,
                                                    unsigned int* counter, float* scratch,
-                                                   long long scratch_stride) {
+                                                   long long scratch_stride, int hmax) {
     __shared__ int16_t qs[kMaxHeight];
     const int lane = threadIdx.x;
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+    (void)hmax;
     for (;;) {
         int t = 0;
         if (lane == 0) t = (int)atomicAdd(counter, 1u);
@@ -196,13 +198,14 @@ void* batch_kernel_for(int slots) {
 }
 
 hipError_t launch_batch(int slots, int grid, hipStream_t st, const JobDesc* jobs, const int2* tasks,
-                        int ntasks, unsigned int* counter, float* scratch, long long stride) {
+                        int ntasks, unsigned int* counter, float* scratch, long long stride,
+                        int hmax) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     switch (slots) {
 #define STX_CASE(n)                                                                        \
     case n:                                                                                \
         hipLaunchKernelGGL(batch_kernel<n>, dim3(grid), dim3(64), 0, st, jobs, tasks,      \
-                           ntasks, counter, scratch, stride);                              \
+                           ntasks, counter, scratch, stride, hmax);                        \
         break;
         STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
         STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
@@ -257,7 +260,7 @@ int occupancy_grid(stixels_batch* b, int slots, int* grid) {
 // Validate the jobs and fill the pinned staging buffers: descriptors and the
 // task list in decreasing-height order.
 int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int* ntasks,
-          long long* stride) {
+          long long* stride, int* hmax_out) {
     if (!jobs || n < 1 || n > b->cfg.max_jobs)
         return bfail(b, STIXELS_E_INVALID_ARG, "job count outside [1, max_jobs]");
     int hmax = 0, dmax = 0;
@@ -321,6 +324,7 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     *slots = (hmax + 63) / 64;
     *ntasks = t;
     *stride = (long long)(4 + dmax) * (hmax + 1);
+    *hmax_out = hmax;
     return STIXELS_OK;
 }
 
@@ -424,16 +428,16 @@ int stixels_batch_destroy(stixels_batch* b) {
 
 int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, void* stream) {
     if (!b) return STIXELS_E_INVALID_ARG;
-    int slots = 0, ntasks = 0, grid = 0;
+    int slots = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &ntasks, &stride);
+    int rc = stage(b, jobs, n, &slots, &ntasks, &stride, &hmax);
     if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
     const hipError_t e = launch_batch(slots, grid, st, b->d_jobs, b->d_tasks, ntasks,
-                                      b->d_counter, b->d_scratch, stride);
+                                      b->d_counter, b->d_scratch, stride, hmax);
     if (e != hipSuccess)
         return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
     b->last_grid = grid;
@@ -445,9 +449,9 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (!b) return STIXELS_E_INVALID_ARG;
     if (!stream)
         return bfail(b, STIXELS_E_INVALID_ARG, "the null stream cannot be captured; pass a created stream");
-    int slots = 0, ntasks = 0, grid = 0;
+    int slots = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &ntasks, &stride);
+    int rc = stage(b, jobs, n, &slots, &ntasks, &stride, &hmax);
     if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -461,7 +465,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
     const hipError_t e = launch_batch(slots, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
-                                      b->d_counter_g, b->d_scratch, stride);
+                                      b->d_counter_g, b->d_scratch, stride, hmax);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {

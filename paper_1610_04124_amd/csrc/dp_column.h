@@ -18,6 +18,8 @@
 // first-minimum index table.
 #pragma once
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace stx {
@@ -50,6 +52,15 @@ __device__ __forceinline__ float sel_slot(const float (&a)[S], int k) {
     return v;
 }
 
+template <int S>
+__device__ __forceinline__ int sel_slot(const int (&a)[S], int k) {
+    int v = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if ((k >> 6) == s) v = readlane_i(a[s], k & 63);
+    return v;
+}
+
 // Emitted stixel, kept by lane t (t-th stixel found from the top).
 struct RecRegs {
     uint32_t w0, w1;
@@ -73,11 +84,15 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                              const ColumnOut& out) {
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
+    const uint32_t stride4 = (uint32_t)stride * 4u;
     const int fmin = in.fmin, fmax = in.fmax;
-    const uint32_t po_bytes = (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u;
-    const auto po = make_rsrc(in.PO, po_bytes);
+    // The buffer base is moved back by fmin rows so that a clamped mean fc
+    // addresses row fc - fmin of the column's object prefix table directly.
+    const float* po_base = in.PO - (ptrdiff_t)fmin * stride;
+    const auto po = make_rsrc(po_base, (uint32_t)(fmax + 1) * stride4);
     const float eps = P.mean_eps;
     const float INF = inf_f();
+    const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
 
     float eG[S], eS[S], eA[S], eN[S];   // prefix values at k+1 (ground masked above vtop)
     float mO[S], mG[S], mS[S];          // OB^k, GR^k, SK^k so far
@@ -104,63 +119,110 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         eA[s] = in.PA[kk];
         eN[s] = in.PN2[kk];
         const int f = rounded_mean(eA[s], eN[s], eps);
-        const int fi = min(max(f, fmin), fmax) - fmin;
-        mO[s] = buf_load(po, fi * stride + kk) + P.first[0];
+        const int fc = min(max(f, fmin), fmax);
+        mO[s] = buf_load_b(po, __umul24((uint32_t)fc, stride4) + (uint32_t)kk * 4u, 0) +
+                P.first[0];
         fO[s] = f;
         mG[s] = eG[s] + P.first[1];
         mS[s] = eS[s] + P.first[2];
     }
 
-    // Push-form recurrence: step j finalises row j and folds cut b = j+1.
+    // Push-form recurrence: step j finalises row j and folds the stixels
+    // that start at b = j+1 into every row k > j.  A step first computes the
+    // object mean of (b, k) for every slot and issues all object-prefix
+    // gathers, then folds the candidates, so one memory latency is paid per
+    // step instead of one per slot.  Steps where no ground stixel can end at
+    // or below b-1 (b > vtop+1) skip the ground terms.
+    auto step = [&](auto gr_tag, const int sj, const int jl) {
+        constexpr bool GR = decltype(gr_tag)::value;
+        const int b = sj * 64 + jl + 1;
+        const float Co = readlane_f(mO[sj], jl);
+        const float Cg = readlane_f(mG[sj], jl);
+        const float Cs = readlane_f(mS[sj], jl);
+        const int fp = readlane_i(fO[sj], jl);
+        const float bS = readlane_f(eS[sj], jl);
+        const float bA = readlane_f(eA[sj], jl);
+        const float bN = readlane_f(eN[sj], jl);
+        const uint32_t b4 = (uint32_t)b * 4u;
+        float pk[S], pb[S];
+        int fS[S];
+        // gathers of a group of slots are in flight together; groups bound
+        // the registers they hold for tall columns
+        constexpr int G = (S <= 8) ? S : 4;
+        const float XS =
+            fminf(fminf(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+        const float Xoo = Co + P.trans[0][0];
+        const float Xoo_p = Xoo + P.c_ord;
+        const int tord = fp + P.tau_ord;
+        const float Xso = Cs + P.trans[2][0];
+        float XG = INF, Xgo = INF, Xgo_d = INF, Xgo_g = INF;
+        int thi = 0, tlo = 0;
+        if constexpr (GR) {
+            const float bG = readlane_f(eG[sj], jl);
+            const int r = H - 1 - b;                 // top-down row of the stixel base
+            thi = in.fg_hi[r];
+            tlo = in.fg_lo[r];
+            XG = (b <= vtop)
+                ? fminf(fminf(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
+                : INF;
+            Xgo = Cg + P.trans[1][0];
+            Xgo_d = Xgo + P.c_dive;
+            Xgo_g = Xgo + P.c_grav;
+        }
+#pragma unroll
+        for (int g0 = sj; g0 < S; g0 += G) {
+        if (g0 >= nslots) break;
+#pragma unroll
+        for (int s = g0; s < g0 + G && s < S; ++s) {
+            if (s >= nslots) break;
+            const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
+            const int fc = min(max(f, fmin), fmax);
+            const uint32_t off = __umul24((uint32_t)fc, stride4);
+            pk[s] = buf_load_b(po, off + lane4 + (uint32_t)(s * 256), 0);
+            pb[s] = buf_load_b(po, off, b4);
+            fS[s] = f;
+        }
+#pragma unroll
+        for (int s = g0; s < g0 + G && s < S; ++s) {
+            if (s >= nslots) break;
+            const bool act = (s > sj) || (lane > jl);   // rows k > j only
+            const int f = fS[s];
+            const float d = pk[s] - pb[s];
+            const float v1 = (f > tord) ? Xoo_p : Xoo;
+            float pr;
+            if constexpr (GR) {
+                float v2 = (f < tlo) ? Xgo_g : Xgo;
+                v2 = (f > thi) ? Xgo_d : v2;
+                pr = fminf(fminf(v1, v2), Xso);
+            } else {
+                pr = fminf(v1, Xso);
+            }
+            float cO = pr + d;
+            float cS = eS[s] + XS;
+            if (s == sj) {
+                cO = act ? cO : INF;
+                cS = act ? cS : INF;
+            }
+            const bool better = cO < mO[s];
+            mO[s] = better ? cO : mO[s];
+            fO[s] = better ? f : fO[s];
+            mS[s] = fminf(mS[s], cS);
+            if constexpr (GR) {
+                float cG = eG[s] + XG;
+                if (s == sj) cG = act ? cG : INF;
+                mG[s] = fminf(mG[s], cG);
+            }
+        }
+        }
+    };
+
 #pragma unroll
     for (int sj = 0; sj < S; ++sj) {
         const int jend = min(64, H - 1 - sj * 64);
-        for (int jl = 0; jl < jend; ++jl) {
-            const int b = sj * 64 + jl + 1;
-            const float Co = readlane_f(mO[sj], jl);
-            const float Cg = readlane_f(mG[sj], jl);
-            const float Cs = readlane_f(mS[sj], jl);
-            const int fp = readlane_i(fO[sj], jl);
-            const float bG = readlane_f(eG[sj], jl);
-            const float bS = readlane_f(eS[sj], jl);
-            const float bA = readlane_f(eA[sj], jl);
-            const float bN = readlane_f(eN[sj], jl);
-            const int r = H - 1 - b;                 // top-down row of the stixel base
-            const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
-            // predecessor terms shared by all rows k >= b
-            const float XG = (b <= vtop)
-                ? fminf(fminf(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
-                : INF;
-            const float XS =
-                fminf(fminf(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
-            const float Xoo = Co + P.trans[0][0];
-            const float Xoo_p = Xoo + P.c_ord;
-            const int tord = fp + P.tau_ord;
-            const float Xgo = Cg + P.trans[1][0];
-            const float Xgo_d = Xgo + P.c_dive;
-            const float Xgo_g = Xgo + P.c_grav;
-            const float Xso = Cs + P.trans[2][0];
-#pragma unroll
-            for (int s = sj; s < S; ++s) {
-                if (s >= nslots) break;
-                if (s > sj || lane > jl) {
-                    mG[s] = fminf(mG[s], eG[s] + XG);
-                    mS[s] = fminf(mS[s], eS[s] + XS);
-                    const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
-                    const int fi = min(max(f, fmin), fmax) - fmin;
-                    const int kk = min(s * 64 + lane + 1, H);
-                    const float d = buf_load(po, fi * stride + kk) - buf_load(po, fi * stride + b);
-                    const float v1 = (f > tord) ? Xoo_p : Xoo;
-                    float v2 = (f < tlo) ? Xgo_g : Xgo;
-                    v2 = (f > thi) ? Xgo_d : v2;
-                    const float c = fminf(fminf(v1, v2), Xso) + d;
-                    if (c < mO[s]) {
-                        mO[s] = c;
-                        fO[s] = f;
-                    }
-                }
-            }
-        }
+        // steps whose base b = sj*64+jl+1 can still follow a ground stixel
+        const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
+        for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl);
+        for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl);
     }
 
     // ---------------------------------------------------------- backtracking
@@ -195,8 +257,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 float d0;
                 if (cls == 0) {
                     f0 = rounded_mean(kA, kN, eps);
-                    const int fi = min(max(f0, fmin), fmax) - fmin;
-                    d0 = buf_load(po, fi * stride + kk);
+                    const int fc = min(max(f0, fmin), fmax);
+                    d0 = buf_load(po, fc * stride + kk);
                 } else {
                     d0 = (cls == 1) ? kG : kS;
                 }
@@ -216,8 +278,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                     float pen_o = 0.0f, pen_g = 0.0f;
                     if (cls == 0) {
                         f = rounded_mean(kA - eA[s], kN - eN[s], eps);
-                        const int fi = min(max(f, fmin), fmax) - fmin;
-                        data = buf_load(po, fi * stride + kk) - buf_load(po, fi * stride + bb);
+                        const int fc = min(max(f, fmin), fmax);
+                        data = buf_load(po, fc * stride + kk) - buf_load(po, fc * stride + bb);
                         pen_o = (f > fO[s] + P.tau_ord) ? P.c_ord : 0.0f;
                         const int r = inr ? H - 1 - bb : 0;
                         const int thi = in.fg_hi[r], tlo = in.fg_lo[r];

@@ -117,11 +117,13 @@ __device__ __forceinline__ float wave_inclusive_scan(float x) {
 // Rounded mean of a stixel's valid disparities, floor((2S+n)/(2n)), from the
 // prefix differences a = 2S+n and n2 = 2n (both exact integers in FP32).
 // With r = rcp(n2) (relative error <= 2^-23) and eps = d_range * 2^-22,
-// fma(a, r, eps) lies in [m, m+1) for a/n2 in [m, m+1) whenever
-// 2n * d_range < 2^24 / 7, which handle creation enforces.  n = 0 gives 0.
+// fma(a, r, eps) lies in [m, m+1) whenever a / n2 lies in [m, m+1) and
+// 2n * d_range < 2^24 / 7, which handle creation enforces (h * d_range <=
+// 2^20).  n = 0 gives a = 0 and f = 0.  The result is >= eps > 0, so
+// truncation is the floor.
 __device__ __forceinline__ int rounded_mean(float a, float n2, float eps) {
     const float r = __builtin_amdgcn_rcpf(fmaxf(n2, 1.0f));
-    return (int)floorf(__builtin_fmaf(a, r, eps));
+    return (int)__builtin_fmaf(a, r, eps);
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
@@ -133,6 +135,12 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
 // index past the resource's size reads 0 instead of faulting.
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, int idx) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, idx * 4, 0, 0));
+}
+
+// Same with a per-lane byte offset and a wave-uniform byte offset (SGPR).
+__device__ __forceinline__ float buf_load_b(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
 }  // namespace stx

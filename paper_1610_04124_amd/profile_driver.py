@@ -1,0 +1,70 @@
+"""Small workload driver for rocprofv3 runs.
+
+    python -m paper_1610_04124_amd.profile_driver --mode batch --launches 3
+    python -m paper_1610_04124_amd.profile_driver --mode frame --launches 3
+    python -m paper_1610_04124_amd.profile_driver --mode copy
+
+batch: the persistent batched launch over 64 synthetic 1024x440 frames
+       (stixel width 5), replayed from a HIP graph;
+frame: the per-frame path (three kernels) on the same frames;
+copy:  a plain 256 MiB device-to-device copy, whose FETCH_SIZE / WRITE_SIZE
+       readings calibrate the HBM byte counters.
+"""
+
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["batch", "frame", "copy"], default="batch")
+    ap.add_argument("--launches", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=64)
+    args = ap.parse_args()
+
+    import torch
+
+    dev = torch.device("cuda", 0)
+    if args.mode == "copy":
+        n = 256 * 1024 * 1024 // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.launches):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copied {n * 4} bytes x {args.launches}", flush=True)
+        return
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    W, H = 1024, 440
+    params = synth.make_params()
+    h = P.Stixels(params)
+    frames = [torch.from_numpy(synth.generate_frame(synth.SceneSpec(seed=i))).to(dev)
+              for i in range(args.frames)]
+    outs = [h.new_output(W, H) for _ in frames]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    if args.mode == "batch":
+        b = P.Batch(len(frames), len(frames) * (W // 5), H, 128)
+        b.capture(list(zip([h] * len(frames), frames, outs)), stream)
+        for _ in range(args.launches):
+            b.replay(stream)
+    else:
+        for _ in range(args.launches):
+            for f, o in zip(frames, outs):
+                h.compute(f, o, stream)
+    torch.cuda.synchronize()
+    print(f"{args.mode}: {args.launches} launches over {len(frames)} frames", flush=True)
+
+
+if __name__ == "__main__":
+    main()
