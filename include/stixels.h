@@ -192,6 +192,11 @@ int stixels_batch_compute(stixels_batch *b, const stixels_job *jobs, int32_t n, 
 int stixels_batch_capture(stixels_batch *b, const stixels_job *jobs, int32_t n, void *stream);
 int stixels_batch_replay(stixels_batch *b, void *stream);
 
+/* Cap on the persistent workgroups of later calls (0 = as many as the
+ * device keeps resident and the batch's scratch allows); used by the
+ * autotuner.  Takes effect at the next compute or capture. */
+int stixels_batch_set_workgroups(stixels_batch *b, int32_t workgroups);
+
 /* Workgroups of the persistent launch last used, and the number of
  * tasks (frame columns) of the last call. */
 int stixels_batch_info(const stixels_batch *b, int32_t *workgroups, int32_t *tasks);

@@ -1,0 +1,106 @@
+"""Autotuner of the persistent batched launch.
+
+The tunable is the number of resident single-wave workgroups of the
+persistent kernel.  More workgroups hide more latency; fewer leave each
+SIMD less contended and shorten the tail when the column tasks do not divide
+evenly into the resident set.  For a job list the tuner captures the launch
+once per candidate, times a few graph replays with HIP events, keeps the
+fastest, and caches the choice on disk keyed by the device and the job
+signature (the multiset of frame height, width, stixel width and d_range).
+Results never depend on the choice: every candidate computes the same bits.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import statistics
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "stixels_autotune.json")
+
+
+def signature(items) -> str:
+    shapes = {}
+    for h, disp, _ in items:
+        H, W = disp.shape
+        key = f"{H}x{W}/s{h.s}/d{h.D}"
+        shapes[key] = shapes.get(key, 0) + 1
+    return ";".join(f"{k}*{n}" for k, n in sorted(shapes.items()))
+
+
+def device_key() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}"
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(max_workgroups: int, ntasks: int):
+    """Grid sizes to try: the resident maximum, fractions of it, and the
+    sizes that split the tasks into whole rounds."""
+    out = set()
+    for frac in (1.0, 0.875, 0.75, 0.625, 0.5):
+        out.add(max(1, int(max_workgroups * frac)))
+    rounds = -(-ntasks // max_workgroups)
+    for r in (rounds, rounds + 1):
+        out.add(max(1, -(-ntasks // r)))
+    return sorted(g for g in out if g <= max_workgroups)
+
+
+def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAULT_CACHE,
+         force: bool = False) -> dict:
+    """Pick and apply the workgroup count for `items` on `batch`; returns the
+    record (also cached).  Leaves the batch captured with the chosen grid."""
+    import torch
+
+    key = device_key() + "||" + signature(items)
+    cache = _load(cache_path) if cache_path else {}
+    if not force and key in cache:
+        rec = cache[key]
+        batch.set_workgroups(rec["workgroups"])
+        batch.capture(items, stream)
+        return dict(rec, cached=True)
+
+    batch.set_workgroups(0)
+    batch.capture(items, stream)
+    gmax, ntasks = batch.info()
+    timings = {}
+    for g in candidates(gmax, ntasks):
+        batch.set_workgroups(g)
+        batch.capture(items, stream)
+        batch.replay(stream)                      # warm
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(replays):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            batch.replay(stream)
+            b.record(stream)
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        timings[g] = statistics.median(ms)
+    best = min(timings, key=timings.get)
+    batch.set_workgroups(best)
+    batch.capture(items, stream)
+    rec = {"workgroups": best, "ms": timings[best], "tasks": ntasks, "max_workgroups": gmax,
+           "tried": {str(k): round(v, 4) for k, v in sorted(timings.items())}}
+    if cache_path:
+        cache[key] = rec
+        _store(cache_path, cache)
+    return dict(rec, cached=False)

@@ -27,6 +27,7 @@ EXPORTS = (
     "stixels_compute", "stixels_last_error", "stixels_status_string",
     "stixels_batch_create", "stixels_batch_destroy", "stixels_batch_compute",
     "stixels_batch_capture", "stixels_batch_replay", "stixels_batch_info",
+    "stixels_batch_set_workgroups",
     "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
     "stixels_debug_stage", "stixels_selftest_mean",
 )
@@ -113,6 +114,7 @@ def lib():
         L.stixels_batch_capture.argtypes = [vp, P(Job), i32, vp]
         L.stixels_batch_replay.argtypes = [vp, vp]
         L.stixels_batch_info.argtypes = [vp, P(i32), P(i32)]
+        L.stixels_batch_set_workgroups.argtypes = [vp, i32]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
         _lib = L
@@ -388,6 +390,11 @@ class Batch:
         rc = lib().stixels_batch_replay(self.b, _stream_ptr(stream))
         if rc != OK:
             self._err(rc, "stixels_batch_replay")
+
+    def set_workgroups(self, n: int):
+        rc = lib().stixels_batch_set_workgroups(self.b, int(n))
+        if rc != OK:
+            self._err(rc, "stixels_batch_set_workgroups")
 
     def info(self):
         g, t = C.c_int32(), C.c_int32()

@@ -101,6 +101,7 @@ void release(stixels_handle* h) {
     (void)hipFree(h->d_sky);
     (void)hipFree(h->d_ground);
     (void)hipFree(h->d_object_t);
+    (void)hipFree(h->d_object_df);
     (void)hipFree(h->d_fg_hi);
     (void)hipFree(h->d_fg_lo);
     (void)hipFree(h->d_q);
@@ -150,6 +151,9 @@ int build_tables(stixels_handle* h) {
         for (int d = 0; d < D; ++d)
             h->object_t[(size_t)f * D + d] = keep(to_grid(pixel_cost(d, f, so, m.p_out, dr), g));
     }
+    h->object_df.resize((size_t)D * D);
+    for (int f = 0; f < D; ++f)
+        for (int d = 0; d < D; ++d) h->object_df[(size_t)d * D + f] = h->object_t[(size_t)f * D + d];
     // priors
     const double beta = to_grid(m.bic_cost, g);
     double fmaxp = 0.0, tmaxp = 0.0;
@@ -211,6 +215,7 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     if (rc == STIXELS_OK) rc = upload(h, &h->d_sky, h->sky);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_ground, h->ground);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_object_t, h->object_t);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_object_df, h->object_df);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_hi, h->fg_hi);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_lo, h->fg_lo);
     if (rc == STIXELS_OK) {

@@ -30,6 +30,7 @@ struct JobDesc {
     const float* sky;
     const float* ground;
     const float* object_t;
+    const float* object_df;
     const int32_t* fg_hi;
     const int32_t* fg_lo;
     int32_t* counts;
@@ -71,6 +72,7 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
                                                    unsigned int* counter, float* scratch,
                                                    long long scratch_stride, int hmax) {
     __shared__ int16_t qs[kMaxHeight];
+    __shared__ float qtab[kMaxDisparity];
     const int lane = threadIdx.x;
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
     (void)hmax;
@@ -85,6 +87,7 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
 
         // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
         int lmin = INT_MAX, lmax = -1;
+        bool inv = false;
         for (int base = 0; base < H; base += 64) {
             const int v = base + lane;
             if (v < H) {
@@ -95,10 +98,16 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
                 if (x >= 0) {
                     lmin = min(lmin, x);
                     lmax = max(lmax, x);
+                } else {
+                    inv = true;
                 }
             }
         }
-        int fmin = wave_min_i(lmin), fmax = wave_max_i(lmax);
+        // object means lie in [smallest, largest valid q]; a stixel without
+        // valid pixels has mean 0, so the table starts at 0 when the column
+        // holds an invalid pixel
+        int fmin = __ballot(inv) ? 0 : wave_min_i(lmin);
+        int fmax = wave_max_i(lmax);
         if (fmax < 0) {
             fmin = 0;
             fmax = 0;
@@ -166,8 +175,11 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
         in.PA = PA;
         in.PN2 = PN;
         in.PO = PO;
-        in.fmin = fmin;
+        in.fbase = fmin;
         in.fmax = fmax;
+        in.q = qs;
+        in.O_df = J.object_df;
+        in.D = D;
         in.fg_hi = J.fg_hi;
         in.fg_lo = J.fg_lo;
         ColumnOut out;
@@ -176,7 +188,7 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
-        solve_column<S>(H, J.vtop, J.prior, in, out);
+        solve_column<S>(H, J.vtop, J.prior, in, out, qtab);
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
 }
@@ -300,6 +312,7 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
         d.sky = h->d_sky;
         d.ground = h->d_ground;
         d.object_t = h->d_object_t;
+        d.object_df = h->d_object_df;
         d.fg_hi = h->d_fg_hi;
         d.fg_lo = h->d_fg_lo;
         d.counts = j.out.counts;
@@ -487,6 +500,12 @@ int stixels_batch_replay(stixels_batch* b, void* stream) {
     if (!b->exec) return bfail(b, STIXELS_E_INVALID_ARG, "no captured batch to replay");
     if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipGraphLaunch failed");
+    return STIXELS_OK;
+}
+
+int stixels_batch_set_workgroups(stixels_batch* b, int32_t workgroups) {
+    if (!b || workgroups < 0) return STIXELS_E_INVALID_ARG;
+    b->cfg.workgroups = workgroups;
     return STIXELS_OK;
 }
 

@@ -29,8 +29,11 @@ struct ColumnIn {
     const float* PS;        // [H+1] sky cost prefix
     const float* PA;        // [H+1] prefix of 2*q+1 over valid pixels
     const float* PN2;       // [H+1] prefix of 2 over valid pixels
-    const float* PO;        // [fmax-fmin+1][H+1] object cost prefix, row f-fmin
-    int fmin, fmax;
+    const float* PO;        // [fmax-fbase+1][H+1] object cost prefix, row f-fbase
+    int fbase, fmax;        // disparity rows of PO (fbase = 0 if the column has an invalid pixel)
+    const int16_t* q;       // [H] reduced disparities of the column (LDS), -1 invalid
+    const float* O_df;      // [D][D] object cost, row d (pixel disparity), column f (mean)
+    int D;
     const int32_t* fg_hi;   // diving threshold per top-down image row
     const int32_t* fg_lo;   // gravity threshold per top-down image row
 };
@@ -52,15 +55,6 @@ __device__ __forceinline__ float sel_slot(const float (&a)[S], int k) {
     return v;
 }
 
-template <int S>
-__device__ __forceinline__ int sel_slot(const int (&a)[S], int k) {
-    int v = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        if ((k >> 6) == s) v = readlane_i(a[s], k & 63);
-    return v;
-}
-
 // Emitted stixel, kept by lane t (t-th stixel found from the top).
 struct RecRegs {
     uint32_t w0, w1;
@@ -79,17 +73,16 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
     return c == 0 ? a0 : (c == 1 ? a1 : a2);
 }
 
+// qtab: per-wave LDS scratch of 256 floats.
 template <int S>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out) {
+                             const ColumnOut& out, float* qtab) {
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
-    const int fmin = in.fmin, fmax = in.fmax;
-    // The buffer base is moved back by fmin rows so that a clamped mean fc
-    // addresses row fc - fmin of the column's object prefix table directly.
-    const float* po_base = in.PO - (ptrdiff_t)fmin * stride;
-    const auto po = make_rsrc(po_base, (uint32_t)(fmax + 1) * stride4);
+    const int fbase = in.fbase, fmax = in.fmax;
+    const int nrow = fmax - fbase + 1;               // <= d_range <= 256
+    const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
     const float eps = P.mean_eps;
     const float INF = inf_f();
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
@@ -119,23 +112,41 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         eA[s] = in.PA[kk];
         eN[s] = in.PN2[kk];
         const int f = rounded_mean(eA[s], eN[s], eps);
-        const int fc = min(max(f, fmin), fmax);
-        mO[s] = buf_load_b(po, __umul24((uint32_t)fc, stride4) + (uint32_t)kk * 4u, 0) +
+        mO[s] = buf_load_b(po, __umul24((uint32_t)(f - fbase), stride4) + (uint32_t)kk * 4u, 0) +
                 P.first[0];
         fO[s] = f;
         mG[s] = eG[s] + P.first[1];
         mS[s] = eS[s] + P.first[2];
     }
 
+    // The object prefix column at the current base, PO[fbase + 64c + lane][b],
+    // is kept in registers and advanced by one row of the object cost table
+    // per step (prefetched a step ahead); it never has to be gathered.
+    float pcol[4], orow[4];
+    auto load_orow = [&](int v) {
+        const int qv = in.q[v];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = 64 * c + lane;
+            orow[c] = (qv >= 0 && i < nrow) ? in.O_df[qv * in.D + fbase + i] : 0.0f;
+        }
+    };
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pcol[c] = 0.0f;
+    if (H > 1) load_orow(0);
+
     // Push-form recurrence: step j finalises row j and folds the stixels
-    // that start at b = j+1 into every row k > j.  A step first computes the
-    // object mean of (b, k) for every slot and issues all object-prefix
-    // gathers, then folds the candidates, so one memory latency is paid per
-    // step instead of one per slot.  Steps where no ground stixel can end at
-    // or below b-1 (b > vtop+1) skip the ground terms.
+    // that start at b = j+1 into every row k > j.  Per step, the prior of an
+    // object stixel with mean f (min over the three predecessor classes,
+    // with the ordering / diving / gravity penalties) minus PO[f][b] is
+    // tabulated once over the column's disparity rows in LDS; a candidate is
+    // then that entry plus one gathered PO[f][k+1].  All slots' gathers are
+    // issued before any candidate is folded.  Steps where no ground stixel
+    // can end at or below b-1 (b > vtop+1) skip the ground terms.
     auto step = [&](auto gr_tag, const int sj, const int jl) {
         constexpr bool GR = decltype(gr_tag)::value;
-        const int b = sj * 64 + jl + 1;
+        const int j = sj * 64 + jl;
+        const int b = j + 1;
         const float Co = readlane_f(mO[sj], jl);
         const float Cg = readlane_f(mG[sj], jl);
         const float Cs = readlane_f(mS[sj], jl);
@@ -143,12 +154,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         const float bS = readlane_f(eS[sj], jl);
         const float bA = readlane_f(eA[sj], jl);
         const float bN = readlane_f(eN[sj], jl);
-        const uint32_t b4 = (uint32_t)b * 4u;
-        float pk[S], pb[S];
-        int fS[S];
-        // gathers of a group of slots are in flight together; groups bound
-        // the registers they hold for tall columns
-        constexpr int G = (S <= 8) ? S : 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pcol[c] += orow[c];      // PO[.][j+1]
+        if (b < H - 1) load_orow(b);                          // row q_{j+1} for the next step
+
         const float XS =
             fminf(fminf(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
         const float Xoo = Co + P.trans[0][0];
@@ -170,24 +179,9 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             Xgo_g = Xgo + P.c_grav;
         }
 #pragma unroll
-        for (int g0 = sj; g0 < S; g0 += G) {
-        if (g0 >= nslots) break;
-#pragma unroll
-        for (int s = g0; s < g0 + G && s < S; ++s) {
-            if (s >= nslots) break;
-            const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
-            const int fc = min(max(f, fmin), fmax);
-            const uint32_t off = __umul24((uint32_t)fc, stride4);
-            pk[s] = buf_load_b(po, off + lane4 + (uint32_t)(s * 256), 0);
-            pb[s] = buf_load_b(po, off, b4);
-            fS[s] = f;
-        }
-#pragma unroll
-        for (int s = g0; s < g0 + G && s < S; ++s) {
-            if (s >= nslots) break;
-            const bool act = (s > sj) || (lane > jl);   // rows k > j only
-            const int f = fS[s];
-            const float d = pk[s] - pb[s];
+        for (int c = 0; c < 4; ++c) {
+            if (64 * c >= nrow) break;
+            const int f = fbase + 64 * c + lane;
             const float v1 = (f > tord) ? Xoo_p : Xoo;
             float pr;
             if constexpr (GR) {
@@ -197,23 +191,49 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             } else {
                 pr = fminf(v1, Xso);
             }
-            float cO = pr + d;
-            float cS = eS[s] + XS;
-            if (s == sj) {
-                cO = act ? cO : INF;
-                cS = act ? cS : INF;
+            qtab[64 * c + lane] = pr - pcol[c];
+        }
+        __syncthreads();
+
+        float pk[S], qv[S];
+        int fS[S];
+        // gathers of a group of slots are in flight together; groups bound
+        // the registers they hold for tall columns
+        constexpr int G = (S <= 8) ? S : 4;
+#pragma unroll
+        for (int g0 = sj; g0 < S; g0 += G) {
+            if (g0 >= nslots) break;
+#pragma unroll
+            for (int s = g0; s < g0 + G && s < S; ++s) {
+                if (s >= nslots) break;
+                const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
+                const uint32_t fi = (uint32_t)(f - fbase);
+                pk[s] = buf_load_b(po, __umul24(fi, stride4) + lane4 + (uint32_t)(s * 256), 0);
+                qv[s] = qtab[fi & 255u];
+                fS[s] = f;
             }
-            const bool better = cO < mO[s];
-            mO[s] = better ? cO : mO[s];
-            fO[s] = better ? f : fO[s];
-            mS[s] = fminf(mS[s], cS);
-            if constexpr (GR) {
-                float cG = eG[s] + XG;
-                if (s == sj) cG = act ? cG : INF;
-                mG[s] = fminf(mG[s], cG);
+#pragma unroll
+            for (int s = g0; s < g0 + G && s < S; ++s) {
+                if (s >= nslots) break;
+                const bool act = (s > sj) || (lane > jl);   // rows k > j only
+                float cO = qv[s] + pk[s];
+                float cS = eS[s] + XS;
+                if (s == sj) {
+                    cO = act ? cO : INF;
+                    cS = act ? cS : INF;
+                }
+                const bool better = cO < mO[s];
+                mO[s] = better ? cO : mO[s];
+                fO[s] = better ? fS[s] : fO[s];
+                mS[s] = fminf(mS[s], cS);
+                if constexpr (GR) {
+                    float cG = eG[s] + XG;
+                    if (s == sj) cG = act ? cG : INF;
+                    mG[s] = fminf(mG[s], cG);
+                }
             }
         }
-        }
+        __syncthreads();   // this step's table reads finish before the next step rewrites it
     };
 
 #pragma unroll
@@ -257,8 +277,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 float d0;
                 if (cls == 0) {
                     f0 = rounded_mean(kA, kN, eps);
-                    const int fc = min(max(f0, fmin), fmax);
-                    d0 = buf_load(po, fc * stride + kk);
+                    d0 = buf_load(po, (f0 - fbase) * stride + kk);
                 } else {
                     d0 = (cls == 1) ? kG : kS;
                 }
@@ -278,8 +297,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                     float pen_o = 0.0f, pen_g = 0.0f;
                     if (cls == 0) {
                         f = rounded_mean(kA - eA[s], kN - eN[s], eps);
-                        const int fc = min(max(f, fmin), fmax);
-                        data = buf_load(po, fc * stride + kk) - buf_load(po, fc * stride + bb);
+                        // lanes past the row (!inr) may form a negative row
+                        // offset: the buffer bounds check turns it into 0
+                        data = buf_load(po, (f - fbase) * stride + kk) -
+                               buf_load(po, (f - fbase) * stride + bb);
                         pen_o = (f > fO[s] + P.tau_ord) ? P.c_ord : 0.0f;
                         const int r = inr ? H - 1 - bb : 0;
                         const int thi = in.fg_hi[r], tlo = in.fg_lo[r];

@@ -61,28 +61,35 @@ struct TablesArgs {
 
 __global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
     __shared__ int16_t qs[kMaxHeight];
-    __shared__ int smin, smax;
+    __shared__ int smin, smax, sinv;
     const int col = blockIdx.x;
     const int H = a.H, D = a.D, ncols = a.ncols;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) {
         smin = INT_MAX;
         smax = -1;
+        sinv = 0;
     }
     __syncthreads();
-    int lmin = INT_MAX, lmax = -1;
+    int lmin = INT_MAX, lmax = -1, linv = 0;
     for (int v = tid; v < H; v += 256) {
         const int x = a.q[(size_t)col * H + v];
         qs[v] = (int16_t)x;
         if (x >= 0) {
             lmin = min(lmin, x);
             lmax = max(lmax, x);
+        } else {
+            linv = 1;
         }
     }
     atomicMin(&smin, lmin);
     atomicMax(&smax, lmax);
+    atomicOr(&sinv, linv);
     __syncthreads();
-    int fmin = smin, fmax = smax;
+    // Object means of the column's stixels lie in [smallest, largest valid
+    // q]; a stixel without valid pixels has mean 0, so the table also starts
+    // at 0 when the column holds an invalid pixel.
+    int fmin = sinv ? 0 : smin, fmax = smax;
     if (fmax < 0) {
         fmin = 0;
         fmax = 0;
@@ -149,6 +156,8 @@ __global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
 
 // ------------------------------------------------------------------ dp
 struct DpArgs {
+    const int16_t* q;
+    const float* object_df;
     const float* prefix;
     const int32_t* range;
     const float* po;
@@ -164,16 +173,23 @@ struct DpArgs {
 
 template <int S>
 __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
+    __shared__ int16_t qs[kMaxHeight];
+    __shared__ float qtab[kMaxDisparity];
     const int col = blockIdx.x;
     const int stride = a.H + 1;
+    for (int v = threadIdx.x; v < a.H; v += 64) qs[v] = a.q[(size_t)col * a.H + v];
+    __syncthreads();
     ColumnIn in;
     in.PG = a.prefix + ((size_t)0 * a.ncols + col) * stride;
     in.PS = a.prefix + ((size_t)1 * a.ncols + col) * stride;
     in.PA = a.prefix + ((size_t)2 * a.ncols + col) * stride;
     in.PN2 = a.prefix + ((size_t)3 * a.ncols + col) * stride;
     in.PO = a.po + (size_t)col * a.D * stride;
-    in.fmin = a.range[2 * col];
+    in.fbase = a.range[2 * col];
     in.fmax = a.range[2 * col + 1];
+    in.q = qs;
+    in.O_df = a.object_df;
+    in.D = a.D;
     in.fg_hi = a.fg_hi;
     in.fg_lo = a.fg_lo;
     ColumnOut out;
@@ -182,7 +198,7 @@ __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
     out.total = a.total + col;
     out.overflow = a.overflow + col;
     out.cap = a.cap;
-    solve_column<S>(a.H, a.vtop, a.prior, in, out);
+    solve_column<S>(a.H, a.vtop, a.prior, in, out, qtab);
 }
 
 // ------------------------------------------------------------------ self-test
@@ -250,6 +266,8 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
 hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
                      const FrameOutput& out, hipStream_t st) {
     DpArgs a;
+    a.q = ws.q;
+    a.object_df = m.object_df;
     a.prefix = ws.prefix;
     a.range = ws.range;
     a.po = ws.po;

@@ -13,12 +13,13 @@ struct stixels_handle {
     int D = 0, Hmax = 0, Wmax = 0, s = 0, ncols_max = 0;
     int device = 0;
     // host copies of the rounded tables
-    std::vector<float> sky, ground, object_t;
+    std::vector<float> sky, ground, object_t, object_df;
     std::vector<int32_t> fg_hi, fg_lo;
     // device tables
     float* d_sky = nullptr;
     float* d_ground = nullptr;
     float* d_object_t = nullptr;
+    float* d_object_df = nullptr;
     int32_t* d_fg_hi = nullptr;
     int32_t* d_fg_lo = nullptr;
     // per-frame workspace
@@ -33,6 +34,7 @@ struct stixels_handle {
 
 // Device view of a handle's resident tables and priors.
 inline stx::DeviceModel device_model(const stixels_handle* h) {
-    return stx::DeviceModel{h->d_sky, h->d_ground, h->d_object_t, h->d_fg_hi, h->d_fg_lo, h->D,
-                            h->Hmax, h->p.reduce_mode, h->s, h->p.camera.horizon_row, h->prior};
+    return stx::DeviceModel{h->d_sky, h->d_ground, h->d_object_t, h->d_object_df, h->d_fg_hi,
+                            h->d_fg_lo, h->D, h->Hmax, h->p.reduce_mode, h->s,
+                            h->p.camera.horizon_row, h->prior};
 }

@@ -13,6 +13,7 @@ struct DeviceModel {
     const float* sky;       // [D]
     const float* ground;    // [max_height][D], top-down image rows
     const float* object_t;  // [D][D], row f: cost of pixel disparity d for mean f
+    const float* object_df; // [D][D], row d: cost of pixel disparity d for every mean f
     const int32_t* fg_hi;   // [max_height], top-down image rows
     const int32_t* fg_lo;
     int D;

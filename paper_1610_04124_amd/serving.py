@@ -1,0 +1,274 @@
+"""Continuous-batching request loop for many camera streams.
+
+Frames arrive from several cameras (each camera: one handle, i.e. its model
+and offline tables resident in HBM).  Each request is admitted as soon as a
+launch slot and HBM are free for it, and every admitted request that is
+waiting when a launch slot frees up joins the next batched launch.  Launches
+go out on several streams, so a batch admitted while others run overlaps
+them on the device.  Admission charges each frame's HBM footprint (input,
+outputs, and the transient reduced column, prefix and object prefix tables)
+against a budget.  Latency is measured from arrival to completion.
+
+The loop is written against a small executor interface, so the admission
+and batching logic can run against a mock executor on the CPU; the GPU
+executor issues stixels_batch_compute on HIP streams.
+"""
+
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+
+@dataclass
+class CameraSpec:
+    handle: object            # paper_1610_04124_amd.Stixels (or a stand-in for the mock)
+    width: int
+    height: int
+
+    def ncols(self) -> int:
+        return self.width // self.handle.s
+
+    def footprint(self) -> int:
+        """HBM bytes a frame of this camera holds while admitted."""
+        ncols, H, D = self.ncols(), self.height, self.handle.D
+        inp = 4 * self.width * H
+        out = ncols * (4 + 12 * H + 4 + 1)
+        transient = ncols * (2 * H + 4 * 4 * (H + 1) + 8 + 4 * D * (H + 1))
+        return inp + out + transient
+
+
+@dataclass(eq=False)
+class Request:
+    rid: int
+    camera: int
+    frame: object             # device tensor [H, W] (or any token for the mock)
+    arrival: float
+    admitted: float = math.nan
+    done: float = math.nan
+    out: object = None
+    cancelled: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class GpuExecutor:
+    """Batched launches on `streams` HIP streams, one batch object each."""
+
+    def __init__(self, cameras, streams: int = 3, max_frames: int = 64):
+        import torch
+
+        import paper_1610_04124_amd as P
+
+        self.cameras = cameras
+        hmax = max(c.height for c in cameras)
+        dmax = max(c.handle.D for c in cameras)
+        tmax = max_frames * max(c.ncols() for c in cameras)
+        self.max_frames = max_frames
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.batches = [P.Batch(max_frames, tmax, hmax, dmax) for _ in range(streams)]
+        self.free = list(range(streams))
+        self._torch = torch
+        self._P = P
+
+    def slots(self) -> int:
+        return len(self.free)
+
+    def launch(self, reqs):
+        """Allocate the requests' outputs and enqueue one batched launch, both
+        on the same stream (the allocation's zero fill is stream-ordered
+        before the kernel that writes the results)."""
+        i = self.free.pop()
+        st = self.streams[i]
+        with self._torch.cuda.stream(st):
+            for r in reqs:
+                c = self.cameras[r.camera]
+                r.out = c.handle.new_output(c.width, c.height)
+        items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in reqs]
+        self.batches[i].compute(items, st)
+        ev = self._torch.cuda.Event()
+        ev.record(st)
+        return (i, ev)
+
+    def finished(self, token) -> bool:
+        i, ev = token
+        if ev.query():
+            self.free.append(i)
+            return True
+        return False
+
+
+class Server:
+    """Admission by HBM footprint + continuous batching over an executor."""
+
+    def __init__(self, cameras, executor, hbm_budget: int, max_batch: int = 64,
+                 clock=time.perf_counter, keep_outputs: bool = True):
+        self.cameras = cameras
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_batch = int(max_batch)
+        self.clock = clock
+        self.queue = collections.deque()
+        self.inflight = []           # (token, [requests], bytes)
+        self.in_use = 0
+        self.completed = []
+        self.rejected = []
+        self._next = 0
+        self.launches = 0
+        self.max_in_use = 0
+        self.max_inflight = 0
+        self.keep_outputs = keep_outputs
+        for c in cameras:
+            if c.footprint() > self.budget:
+                raise ValueError("HBM budget smaller than one frame of a camera")
+
+    # ---------------------------------------------------------------- API
+    def submit(self, camera: int, frame, arrival: float | None = None) -> Request | None:
+        """Queue a frame; malformed requests are rejected (returns None)."""
+        t = self.clock() if arrival is None else arrival
+        ok = 0 <= camera < len(self.cameras)
+        if ok and hasattr(frame, "shape"):
+            c = self.cameras[camera]
+            ok = tuple(frame.shape) == (c.height, c.width)
+        r = Request(self._next, camera, frame, t)
+        self._next += 1
+        if not ok:
+            self.rejected.append(r)
+            return None
+        self.queue.append(r)
+        return r
+
+    def cancel(self, req: Request) -> bool:
+        """Drop a request that has not been admitted yet."""
+        if req in self.queue:
+            self.queue.remove(req)
+            req.cancelled = True
+            return True
+        return False
+
+    def poll(self) -> int:
+        """Retire finished launches, then admit and launch waiting requests.
+        Returns the number of requests launched."""
+        now = self.clock()
+        still = []
+        for tok, reqs, nbytes in self.inflight:
+            if self.ex.finished(tok):
+                t = self.clock()
+                for r in reqs:
+                    r.done = t
+                    if not self.keep_outputs:
+                        r.out = None
+                self.completed.extend(reqs)
+                self.in_use -= nbytes
+            else:
+                still.append((tok, reqs, nbytes))
+        self.inflight = still
+        launched = 0
+        while self.queue and self.ex.slots() > 0:
+            batch, nbytes = [], 0
+            while self.queue and len(batch) < self.max_batch:
+                r = self.queue[0]
+                fp = self.cameras[r.camera].footprint()
+                if self.in_use + nbytes + fp > self.budget:
+                    break
+                self.queue.popleft()
+                batch.append(r)
+                nbytes += fp
+            if not batch:
+                break
+            for r in batch:
+                r.admitted = now
+            tok = self.ex.launch(batch)
+            self.in_use += nbytes
+            self.max_in_use = max(self.max_in_use, self.in_use)
+            self.inflight.append((tok, batch, nbytes))
+            self.max_inflight = max(self.max_inflight, len(self.inflight))
+            self.launches += 1
+            launched += len(batch)
+        return launched
+
+    def drain(self, timeout: float = 60.0) -> None:
+        t_end = self.clock() + timeout
+        while (self.queue or self.inflight) and self.clock() < t_end:
+            self.poll()
+        if self.queue or self.inflight:
+            raise TimeoutError("server did not drain")
+
+    # ---------------------------------------------------------------- driver
+    def run_trace(self, arrivals, frames_of) -> None:
+        """Replay `arrivals` (sorted (time_offset, camera, index)) in real
+        time: each request is submitted when its arrival time is reached."""
+        t0 = self.clock()
+        i = 0
+        n = len(arrivals)
+        while i < n or self.queue or self.inflight:
+            now = self.clock() - t0
+            while i < n and arrivals[i][0] <= now:
+                off, cam, idx = arrivals[i]
+                self.submit(cam, frames_of(cam, idx), arrival=t0 + off)
+                i += 1
+            self.poll()
+
+    def stats(self) -> dict:
+        lat = sorted(r.latency for r in self.completed)
+
+        def pct(q):
+            if not lat:
+                return None
+            k = (len(lat) - 1) * q
+            lo = int(k)
+            hi = min(lo + 1, len(lat) - 1)
+            return lat[lo] + (lat[hi] - lat[lo]) * (k - lo)
+
+        span = (max(r.done for r in self.completed) - min(r.arrival for r in self.completed)
+                if self.completed else 0.0)
+        return {"completed": len(self.completed), "rejected": len(self.rejected),
+                "launches": self.launches,
+                "frames_per_launch": len(self.completed) / max(self.launches, 1),
+                "throughput_fps": len(self.completed) / span if span > 0 else None,
+                "latency_ms_p50": None if not lat else 1e3 * pct(0.5),
+                "latency_ms_p99": None if not lat else 1e3 * pct(0.99),
+                "peak_hbm_in_use": self.max_in_use, "max_launches_in_flight": self.max_inflight}
+
+
+def poisson_arrivals(rates, seconds: float, seeds, frames_per_camera: int):
+    """Merged arrival list of independent Poisson streams (rates in Hz):
+    sorted (time, camera, frame index)."""
+    import numpy as np
+
+    out = []
+    for cam, (rate, seed) in enumerate(zip(rates, seeds)):
+        rng = np.random.default_rng(seed)
+        t = 0.0
+        n = 0
+        while True:
+            t += rng.exponential(1.0 / rate)
+            if t >= seconds:
+                break
+            out.append((t, cam, n % frames_per_camera))
+            n += 1
+    out.sort()
+    return out
+
+
+# config of the serving workload: 8 cameras, frame size by camera index
+SERVING_SIZES = [(1024, 440), (1280, 720), (2048, 880)]
+
+
+def serving_cameras(n_cameras: int = 8, stixel_width: int = 5):
+    """Handles and frame sizes of the serving workload (one handle per camera)."""
+    import synth
+    import paper_1610_04124_amd as P
+
+    cams = []
+    for i in range(n_cameras):
+        W, H = SERVING_SIZES[i % len(SERVING_SIZES)]
+        D = 256 if W == 2048 else 128
+        p = synth.make_params(camera=synth.camera_for_size(W, H), stixel_width=stixel_width,
+                              max_disparity=D, max_width=W, max_height=H)
+        cams.append(CameraSpec(P.Stixels(p), W, H))
+    return cams
