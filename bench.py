@@ -84,9 +84,47 @@ def cpu_baseline(frames, params, n_frames):
                       f"C FP64 oracle, OpenMP over columns, {dt:.2f} s wall"}
 
 
-def serve(seconds):
+def hires(warmup, steps):
+    """16 frames of 2048x880 (d_range 256) at stixel widths 3 and 5, one
+    batched graph replay per step."""
+    import torch
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    dev = torch.device("cuda", 0)
+    Wh, Hh = 2048, 880
+    cam = synth.camera_for_size(Wh, Hh)
+    frames = [torch.from_numpy(synth.generate_frame(synth.SceneSpec(Wh, Hh, 256, cam, seed=i))).to(dev)
+              for i in range(16)]
+    out = {}
+    stream = torch.cuda.Stream()
+    for s in (3, 5):
+        params = synth.make_params(camera=cam, stixel_width=s, max_disparity=256, max_width=Wh,
+                                   max_height=Hh)
+        h = P.Stixels(params)
+        outs = [h.new_output(Wh, Hh) for _ in frames]
+        b = P.Batch(16, 16 * (Wh // s), Hh, 256)
+        torch.cuda.synchronize()
+        b.capture(list(zip([h] * 16, frames, outs)), stream)
+        for _ in range(warmup):
+            b.replay(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.replay(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        pairs = 16 * (Wh // s) * Hh * (Hh + 1) // 2
+        out[f"s{s}"] = {"fps": round(16 / dt, 2), "ms_per_batch": round(dt * 1e3, 4),
+                        "valu_frac": round(OPS_PER_PAIR * pairs / dt / VALU_PEAK, 4)}
+    return out
+
+
+def serve(seconds, rate_scale=1.0):
     """8 cameras (1024x440, 1280x720, 2048x880 by camera index, stixel width
-    5) at 30 Hz Poisson each, served with continuous batching in real time."""
+    5) at 30 Hz Poisson each (times rate_scale), served with continuous
+    batching in real time."""
     import torch
 
     import synth
@@ -104,13 +142,14 @@ def serve(seconds):
             frames[(c, i)] = torch.from_numpy(synth.generate_frame(spec)).to(dev)
     ex = GpuExecutor(cams, streams=3, max_frames=64)
     srv = Server(cams, ex, hbm_budget=8 << 30, max_batch=64, keep_outputs=False)
-    arrivals = poisson_arrivals([30.0] * 8, seconds, [42 + c for c in range(8)], per_cam)
+    arrivals = poisson_arrivals([30.0 * rate_scale] * 8, seconds, [42 + c for c in range(8)],
+                                per_cam)
     torch.cuda.synchronize()
     srv.run_trace(arrivals, lambda c, i: frames[(c, i)])
     torch.cuda.synchronize()
     st = srv.stats()
     st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
-    st.update({"cameras": 8, "rate_hz_per_camera": 30, "seconds": seconds,
+    st.update({"cameras": 8, "rate_hz_per_camera": 30 * rate_scale, "seconds": seconds,
                "sizes": "1024x440, 1280x720, 2048x880 by camera index; stixel width 5"})
     return st
 
@@ -120,7 +159,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-frames", type=int, default=16)
+    ap.add_argument("--cpu-frames", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--serve-seconds", type=float, default=4.0)
@@ -226,8 +265,11 @@ def main():
     }
     if tuned is not None:
         result["config"]["autotune_tried_ms"] = tuned["tried"]
+    result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5))
     if args.serve_seconds > 0:
         result["serving"] = serve(args.serve_seconds)
+        # the same cameras at 16x the rate: continuous batching under load
+        result["serving_loaded"] = serve(args.serve_seconds / 2, rate_scale=16.0)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(frames, params, args.cpu_frames)
     print(json.dumps(result), flush=True)

@@ -65,7 +65,7 @@ __device__ __forceinline__ int wave_max_i(int x) {
 
 __global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
 
-template <int S>
+template <int S, int NCH>
 __global__ __launch_bounds__(64)
 __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const JobDesc* __restrict__ jobs,
                                                    const int2* __restrict__ tasks, int ntasks,
@@ -188,43 +188,33 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
-        solve_column<S>(H, J.vtop, J.prior, in, out, qtab);
+        solve_column<S, NCH>(H, J.vtop, J.prior, in, out, qtab);
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
 }
 
-template <int S>
-void* kernel_ptr() {
-    return reinterpret_cast<void*>(&batch_kernel<S>);
-}
-
-void* batch_kernel_for(int slots) {
-    switch (slots) {
-#define STX_CASE(n) case n: return kernel_ptr<n>();
-        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
-        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
-        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+void* batch_kernel_for(int slots, int nch) {
+#define STX_CASE(n, c) \
+    if (slots == n && nch == c) return reinterpret_cast<void*>(&batch_kernel<n, c>);
+    STX_FOR_EACH_VARIANT(STX_CASE)
 #undef STX_CASE
-        default: return nullptr;
-    }
+    return nullptr;
 }
 
-hipError_t launch_batch(int slots, int grid, hipStream_t st, const JobDesc* jobs, const int2* tasks,
-                        int ntasks, unsigned int* counter, float* scratch, long long stride,
-                        int hmax) {
+hipError_t launch_batch(int slots, int nch, int grid, hipStream_t st, const JobDesc* jobs,
+                        const int2* tasks, int ntasks, unsigned int* counter, float* scratch,
+                        long long stride, int hmax) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-    switch (slots) {
-#define STX_CASE(n)                                                                        \
-    case n:                                                                                \
-        hipLaunchKernelGGL(batch_kernel<n>, dim3(grid), dim3(64), 0, st, jobs, tasks,      \
-                           ntasks, counter, scratch, stride, hmax);                        \
-        break;
-        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
-        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
-        STX_CASE(14) STX_CASE(15) STX_CASE(16)
-#undef STX_CASE
-        default: return hipErrorInvalidValue;
+    bool launched = false;
+#define STX_CASE(n, c)                                                                   \
+    if (slots == n && nch == c) {                                                        \
+        hipLaunchKernelGGL((batch_kernel<n, c>), dim3(grid), dim3(64), 0, st, jobs, tasks, \
+                           ntasks, counter, scratch, stride, hmax);                      \
+        launched = true;                                                                 \
     }
+    STX_FOR_EACH_VARIANT(STX_CASE)
+#undef STX_CASE
+    if (!launched) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -259,9 +249,9 @@ int bfail(stixels_batch* b, int code, const std::string& m) {
     return code;
 }
 
-int occupancy_grid(stixels_batch* b, int slots, int* grid) {
+int occupancy_grid(stixels_batch* b, int slots, int nch, int* grid) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots), 64, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots, nch), 64, 0) !=
             hipSuccess ||
         per_cu < 1)
         return bfail(b, STIXELS_E_HIP, "occupancy query failed");
@@ -271,8 +261,8 @@ int occupancy_grid(stixels_batch* b, int slots, int* grid) {
 
 // Validate the jobs and fill the pinned staging buffers: descriptors and the
 // task list in decreasing-height order.
-int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int* ntasks,
-          long long* stride, int* hmax_out) {
+int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int* nch,
+          int* ntasks, long long* stride, int* hmax_out) {
     if (!jobs || n < 1 || n > b->cfg.max_jobs)
         return bfail(b, STIXELS_E_INVALID_ARG, "job count outside [1, max_jobs]");
     int hmax = 0, dmax = 0;
@@ -334,16 +324,17 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
         const int nc = b->h_jobs[i].ncols;
         for (int c = 0; c < nc; ++c) b->h_tasks[t++] = make_int2(i, c);
     }
-    *slots = (hmax + 63) / 64;
+    *slots = kernel_slots(hmax);
+    *nch = kernel_chunks(dmax);
     *ntasks = t;
     *stride = (long long)(4 + dmax) * (hmax + 1);
     *hmax_out = hmax;
     return STIXELS_OK;
 }
 
-int choose_grid(stixels_batch* b, int slots, long long stride, int ntasks, int* grid) {
+int choose_grid(stixels_batch* b, int slots, int nch, long long stride, int ntasks, int* grid) {
     int g = 0;
-    int rc = occupancy_grid(b, slots, &g);
+    int rc = occupancy_grid(b, slots, nch, &g);
     if (rc != STIXELS_OK) return rc;
     if (b->cfg.workgroups > 0) g = std::min(g, (int)b->cfg.workgroups);
     const long long by_scratch = (long long)(b->scratch_floats / (size_t)stride);
@@ -394,8 +385,8 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
             hipSuccess)
         rc = STIXELS_E_HIP;
     int grid = 0;
-    const int slots = (cfg->max_height + 63) / 64;
-    if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, &grid);
+    const int slots = kernel_slots(cfg->max_height);
+    if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, kernel_chunks(cfg->max_disparity), &grid);
     if (rc == STIXELS_OK && cfg->workgroups > 0) grid = std::min(grid, (int)cfg->workgroups);
     if (rc == STIXELS_OK) {
         b->scratch_floats = (size_t)grid * (size_t)(4 + cfg->max_disparity) *
@@ -441,15 +432,15 @@ int stixels_batch_destroy(stixels_batch* b) {
 
 int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, void* stream) {
     if (!b) return STIXELS_E_INVALID_ARG;
-    int slots = 0, ntasks = 0, grid = 0, hmax = 0;
+    int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &ntasks, &stride, &hmax);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
+    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
-    const hipError_t e = launch_batch(slots, grid, st, b->d_jobs, b->d_tasks, ntasks,
+    const hipError_t e = launch_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
                                       b->d_counter, b->d_scratch, stride, hmax);
     if (e != hipSuccess)
         return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
@@ -462,10 +453,10 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (!b) return STIXELS_E_INVALID_ARG;
     if (!stream)
         return bfail(b, STIXELS_E_INVALID_ARG, "the null stream cannot be captured; pass a created stream");
-    int slots = 0, ntasks = 0, grid = 0, hmax = 0;
+    int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &ntasks, &stride, &hmax);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, stride, ntasks, &grid);
+    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     // the graph reads its own descriptor copy, uploaded once here
@@ -477,7 +468,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     destroy_graph(b);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
-    const hipError_t e = launch_batch(slots, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+    const hipError_t e = launch_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
                                       b->d_counter_g, b->d_scratch, stride, hmax);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(st, &g);

@@ -73,15 +73,16 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
     return c == 0 ? a0 : (c == 1 ? a1 : a2);
 }
 
-// qtab: per-wave LDS scratch of 256 floats.
-template <int S>
+// qtab: per-wave LDS scratch of 256 floats.  S: 64-row slots per lane
+// (h <= 64 S); NCH: 64-entry chunks of disparity rows (d_range <= 64 NCH).
+template <int S, int NCH>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                              const ColumnOut& out, float* qtab) {
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
     const int fbase = in.fbase, fmax = in.fmax;
-    const int nrow = fmax - fbase + 1;               // <= d_range <= 256
+    const int nrow = fmax - fbase + 1;               // <= d_range <= 64 * NCH
     const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
     const float eps = P.mean_eps;
     const float INF = inf_f();
@@ -122,40 +123,57 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // The object prefix column at the current base, PO[fbase + 64c + lane][b],
     // is kept in registers and advanced by one row of the object cost table
     // per step (prefetched a step ahead); it never has to be gathered.
-    float pcol[4], orow[4];
+    float pcol[NCH], orow[NCH];
+    const int nchunk = (nrow + 63) >> 6;             // 64-row chunks of disparity rows
     auto load_orow = [&](int v) {
         const int qv = in.q[v];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < NCH; ++c) {
+            if (c >= nchunk) break;
             const int i = 64 * c + lane;
             orow[c] = (qv >= 0 && i < nrow) ? in.O_df[qv * in.D + fbase + i] : 0.0f;
         }
     };
 #pragma unroll
-    for (int c = 0; c < 4; ++c) pcol[c] = 0.0f;
+    for (int c = 0; c < NCH; ++c) pcol[c] = orow[c] = 0.0f;
     if (H > 1) load_orow(0);
 
     // Push-form recurrence: step j finalises row j and folds the stixels
-    // that start at b = j+1 into every row k > j.  Per step, the prior of an
-    // object stixel with mean f (min over the three predecessor classes,
-    // with the ordering / diving / gravity penalties) minus PO[f][b] is
-    // tabulated once over the column's disparity rows in LDS; a candidate is
-    // then that entry plus one gathered PO[f][k+1].  All slots' gathers are
-    // issued before any candidate is folded.  Steps where no ground stixel
-    // can end at or below b-1 (b > vtop+1) skip the ground terms.
+    // that start at b = j+1 into every row k > j.  Row j's costs and prefix
+    // values are broadcast from the lane that owns row j.  Per step, the prior
+    // of an object stixel with mean f (min over the three predecessor
+    // classes, with the ordering / diving / gravity penalties) minus
+    // PO[f][b] is tabulated once over the column's disparity rows in LDS; a
+    // candidate is then that entry plus one gathered PO[f][k+1].  All slots'
+    // gathers are issued before any candidate is folded.  Steps where no
+    // ground stixel can end at or below b-1 (b > vtop+1) skip the ground
+    // terms.  Slots below the current row are skipped by uniform branches.
     auto step = [&](auto gr_tag, const int sj, const int jl) {
         constexpr bool GR = decltype(gr_tag)::value;
-        const int j = sj * 64 + jl;
-        const int b = j + 1;
-        const float Co = readlane_f(mO[sj], jl);
-        const float Cg = readlane_f(mG[sj], jl);
-        const float Cs = readlane_f(mS[sj], jl);
-        const int fp = readlane_i(fO[sj], jl);
-        const float bS = readlane_f(eS[sj], jl);
-        const float bA = readlane_f(eA[sj], jl);
-        const float bN = readlane_f(eN[sj], jl);
+        const int j = sj * 64 + jl, b = j + 1;
+        // row j's costs and prefix values, read from its owning lane; the
+        // slot is chosen by wave-uniform branches (an indexed choice would
+        // put the slot registers in scratch memory)
+        float Co = 0.0f, Cg = 0.0f, Cs = 0.0f, bS = 0.0f, bA = 0.0f, bN = 0.0f, bG = 0.0f;
+        int fp = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pcol[c] += orow[c];      // PO[.][j+1]
+        for (int s = 0; s < S; ++s) {
+            if (s == sj) {
+                Co = readlane_f(mO[s], jl);
+                Cg = readlane_f(mG[s], jl);
+                Cs = readlane_f(mS[s], jl);
+                fp = readlane_i(fO[s], jl);
+                bS = readlane_f(eS[s], jl);
+                bA = readlane_f(eA[s], jl);
+                bN = readlane_f(eN[s], jl);
+                bG = readlane_f(eG[s], jl);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            if (c >= nchunk) break;
+            pcol[c] += orow[c];                               // PO[.][j+1]
+        }
         if (b < H - 1) load_orow(b);                          // row q_{j+1} for the next step
 
         const float XS =
@@ -167,7 +185,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         float XG = INF, Xgo = INF, Xgo_d = INF, Xgo_g = INF;
         int thi = 0, tlo = 0;
         if constexpr (GR) {
-            const float bG = readlane_f(eG[sj], jl);
             const int r = H - 1 - b;                 // top-down row of the stixel base
             thi = in.fg_hi[r];
             tlo = in.fg_lo[r];
@@ -179,8 +196,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             Xgo_g = Xgo + P.c_grav;
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (64 * c >= nrow) break;
+        for (int c = 0; c < NCH; ++c) {
+            if (c >= nchunk) break;
             const int f = fbase + 64 * c + lane;
             const float v1 = (f > tord) ? Xoo_p : Xoo;
             float pr;
@@ -201,10 +218,12 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // the registers they hold for tall columns
         constexpr int G = (S <= 8) ? S : 4;
 #pragma unroll
-        for (int g0 = sj; g0 < S; g0 += G) {
+        for (int g0 = 0; g0 < S; g0 += G) {
             if (g0 >= nslots) break;
+            if (g0 + G <= sj) continue;
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
+                if (s < sj) continue;
                 if (s >= nslots) break;
                 const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
                 const uint32_t fi = (uint32_t)(f - fbase);
@@ -214,35 +233,45 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             }
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
+                if (s < sj) continue;
                 if (s >= nslots) break;
                 const bool act = (s > sj) || (lane > jl);   // rows k > j only
                 float cO = qv[s] + pk[s];
                 float cS = eS[s] + XS;
-                if (s == sj) {
-                    cO = act ? cO : INF;
-                    cS = act ? cS : INF;
-                }
+                cO = act ? cO : INF;
+                cS = act ? cS : INF;
                 const bool better = cO < mO[s];
                 mO[s] = better ? cO : mO[s];
                 fO[s] = better ? fS[s] : fO[s];
                 mS[s] = fminf(mS[s], cS);
                 if constexpr (GR) {
                     float cG = eG[s] + XG;
-                    if (s == sj) cG = act ? cG : INF;
+                    cG = act ? cG : INF;
                     mG[s] = fminf(mG[s], cG);
                 }
             }
         }
-        __syncthreads();   // this step's table reads finish before the next step rewrites it
+        __syncthreads();           // this step's table reads finish before the next step rewrites it
     };
 
+    if constexpr (S <= 8) {
+        // unrolled over the slot of row j, so that every slot test above is
+        // decided at compile time and the slots' gathers share one block
 #pragma unroll
-    for (int sj = 0; sj < S; ++sj) {
-        const int jend = min(64, H - 1 - sj * 64);
-        // steps whose base b = sj*64+jl+1 can still follow a ground stixel
-        const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
-        for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl);
-        for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl);
+        for (int sj = 0; sj < S; ++sj) {
+            const int jend = min(64, H - 1 - sj * 64);
+            // steps whose base b = sj*64+jl+1 can still follow a ground stixel
+            const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
+            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl);
+            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl);
+        }
+    } else {
+        // tall columns: one runtime loop keeps the code (and the registers
+        // live across it) to a single copy of the step
+        for (int j = 0; j < H - 1; ++j) {
+            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63);
+            else step(std::false_type{}, j >> 6, j & 63);
+        }
     }
 
     // ---------------------------------------------------------- backtracking

@@ -15,17 +15,18 @@
 namespace stx {
 
 // ------------------------------------------------------------------ reduce
-// One workgroup reduces a tile of 64 columns x 64 image rows.
+// One workgroup reduces a tile of 64 columns x 16 image rows (enough
+// workgroups to spread one frame over the chip).
 template <int S>
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ disp, int W, int H,
                                                      int ncols, int D, int mode,
                                                      int16_t* __restrict__ q) {
-    __shared__ int16_t tile[64][65];
-    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+    __shared__ int16_t tile[64][17];
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 16;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int col = c0 + tx;
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
         const int rl = ty + 4 * i;
         const int r = r0 + rl;
         int v = -1;
@@ -35,12 +36,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ d
     }
     __syncthreads();
     // tile row rl (image row r0+rl) lands at bottom-up row H-1-r: write each
-    // column's 64 rows as one contiguous run of ascending v
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
+    // column's 16 rows as one contiguous run of ascending v
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
         const int e = threadIdx.x + 256 * i;
-        const int cl = e >> 6, vl = e & 63;
-        const int rl = 63 - vl;
+        const int cl = e >> 4, vl = e & 15;
+        const int rl = 15 - vl;
         const int r = r0 + rl;
         const int cg = c0 + cl;
         if (cg < ncols && r < H) q[(size_t)cg * H + (H - 1 - r)] = tile[cl][rl];
@@ -59,7 +60,7 @@ struct TablesArgs {
     int H, ncols, D;
 };
 
-__global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
+__global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
     __shared__ int16_t qs[kMaxHeight];
     __shared__ int smin, smax, sinv;
     const int col = blockIdx.x;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
     }
     __syncthreads();
     int lmin = INT_MAX, lmax = -1, linv = 0;
-    for (int v = tid; v < H; v += 256) {
+    for (int v = tid; v < H; v += 512) {
         const int x = a.q[(size_t)col * H + v];
         qs[v] = (int16_t)x;
         if (x >= 0) {
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(256) void tables_kernel(TablesArgs a) {
     }
 
     float* PO = a.po + (size_t)col * D * stride;
-    for (int f = fmin + wave; f <= fmax; f += 4) {
+    for (int f = fmin + wave; f <= fmax; f += 8) {
         const float* orow = a.object_t + (size_t)f * D;
         float* prow = PO + (size_t)(f - fmin) * stride;
         if (lane == 0) prow[0] = 0.0f;
@@ -171,7 +172,7 @@ struct DpArgs {
     Prior prior;
 };
 
-template <int S>
+template <int S, int NCH>
 __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
     __shared__ int16_t qs[kMaxHeight];
     __shared__ float qtab[kMaxDisparity];
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
     out.total = a.total + col;
     out.overflow = a.overflow + col;
     out.cap = a.cap;
-    solve_column<S>(a.H, a.vtop, a.prior, in, out, qtab);
+    solve_column<S, NCH>(a.H, a.vtop, a.prior, in, out, qtab);
 }
 
 // ------------------------------------------------------------------ self-test
@@ -233,7 +234,7 @@ static void reduce_launch(dim3 g, const DeviceModel& m, const float* disp, int W
 
 hipError_t launch_reduce(const DeviceModel& m, const float* disp, int W, int H, int ncols,
                          int16_t* q, hipStream_t st) {
-    const dim3 g((ncols + 63) / 64, (H + 63) / 64);
+    const dim3 g((ncols + 63) / 64, (H + 15) / 16);
     switch (m.s) {
 #define STX_CASE(n) case n: reduce_launch<n>(g, m, disp, W, H, ncols, q, st); break;
         STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
@@ -259,7 +260,7 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
     a.H = H;
     a.ncols = ncols;
     a.D = m.D;
-    hipLaunchKernelGGL(tables_kernel, dim3(ncols), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(tables_kernel, dim3(ncols), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
@@ -283,16 +284,17 @@ hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int 
     a.D = m.D;
     a.vtop = vtop;
     a.prior = m.prior;
-    const int slots = (H + 63) / 64;
+    const int slots = kernel_slots(H), nch = kernel_chunks(m.D);
     const dim3 g(ncols), b(64);
-    switch (slots) {
-#define STX_CASE(n) case n: hipLaunchKernelGGL(dp_kernel<n>, g, b, 0, st, a); break;
-        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
-        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
-        STX_CASE(14) STX_CASE(15) STX_CASE(16)
-#undef STX_CASE
-        default: return hipErrorInvalidValue;
+    bool launched = false;
+#define STX_CASE(n, c)                                                  \
+    if (slots == n && nch == c) {                                       \
+        hipLaunchKernelGGL((dp_kernel<n, c>), g, b, 0, st, a);          \
+        launched = true;                                                \
     }
+    STX_FOR_EACH_VARIANT(STX_CASE)
+#undef STX_CASE
+    if (!launched) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -26,6 +26,20 @@ constexpr int kMaxStixelWidth = 16;
 constexpr int kMaxDisparity = 256;
 constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
 
+// Instantiated slot counts of the recurrence kernels (64-row slots per lane);
+// a column runs on the smallest one that covers its height.
+__host__ __device__ constexpr int kernel_slots(int h) {
+    const int s = (h + 63) / 64;
+    return s <= 8 ? s : (s <= 10 ? 10 : (s <= 12 ? 12 : (s <= 14 ? 14 : 16)));
+}
+// 64-entry disparity chunks for a d_range.
+__host__ __device__ constexpr int kernel_chunks(int d_range) { return d_range <= 128 ? 2 : 4; }
+
+#define STX_FOR_EACH_VARIANT(X)                                                              \
+    X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2) X(10, 2) X(12, 2)     \
+    X(14, 2) X(16, 2) X(1, 4) X(2, 4) X(3, 4) X(4, 4) X(5, 4) X(6, 4) X(7, 4) X(8, 4)     \
+    X(10, 4) X(12, 4) X(14, 4) X(16, 4)
+
 // Quantised prior constants of one camera model, in FP32 (exact on the grid).
 struct Prior {
     float first[3];       // F[c] + beta

@@ -79,17 +79,24 @@ class GpuExecutor:
         return len(self.free)
 
     def launch(self, reqs):
-        """Allocate the requests' outputs and enqueue one batched launch, both
-        on the same stream (the allocation's zero fill is stream-ordered
-        before the kernel that writes the results)."""
+        """Allocate the requests' outputs and enqueue the batched launches,
+        all on one stream (the allocation's zero fill is stream-ordered before
+        the kernels that write the results).  Frames are grouped by height
+        class (64-row slots per lane of the recurrence), one launch per
+        class, so short frames never run the register-heavy variant sized
+        for tall ones."""
         i = self.free.pop()
         st = self.streams[i]
         with self._torch.cuda.stream(st):
             for r in reqs:
                 c = self.cameras[r.camera]
                 r.out = c.handle.new_output(c.width, c.height)
-        items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in reqs]
-        self.batches[i].compute(items, st)
+        groups = {}
+        for r in reqs:
+            groups.setdefault((self.cameras[r.camera].height + 63) // 64, []).append(r)
+        for slots in sorted(groups, reverse=True):
+            items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in groups[slots]]
+            self.batches[i].compute(items, st)
         ev = self._torch.cuda.Event()
         ev.record(st)
         return (i, ev)

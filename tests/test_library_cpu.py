@@ -143,3 +143,25 @@ def test_record_decoding():
     assert list(d["v_bottom"]) == [5, 18] and list(d["v_top"]) == [17, 439]
     assert list(d["cls"]) == [0, 2] and list(d["disparity"]) == [42, 0]
     assert list(d["cost"]) == [12.5, -0.25]
+
+
+def test_create_and_batch_reject_bad_arguments_without_a_device():
+    """Validation happens before any HIP call, so it runs on the CPU."""
+    import ctypes as C
+    L = P.lib()
+    p = synth.make_params()
+    p["max_height"] = 2000
+    h = C.c_void_p()
+    assert L.stixels_create(C.byref(B.to_params(p)), C.byref(h)) == B.E_INVALID_ARG
+    assert b"max_height" in L.stixels_last_error(None)
+    assert L.stixels_create(None, C.byref(h)) == B.E_INVALID_ARG
+    b = C.c_void_p()
+    for cfg in [(0, 10, 440, 128), (1, 0, 440, 128), (1, 10, 1025, 128), (1, 10, 440, 300),
+                (1, 10, 440, 1)]:
+        c = B.BatchConfig()
+        c.max_jobs, c.max_tasks, c.max_height, c.max_disparity = cfg
+        assert L.stixels_batch_create(C.byref(c), C.byref(b)) == B.E_INVALID_ARG
+    assert L.stixels_destroy(None) == 0 and L.stixels_batch_destroy(None) == 0
+    assert L.stixels_selftest_mean(1, 10, None) == B.E_INVALID_ARG
+    n = C.c_int64()
+    assert L.stixels_selftest_mean(256, 8192, C.byref(n)) == B.E_INVALID_ARG
