@@ -122,21 +122,34 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 
     // The object prefix column at the current base, PO[fbase + 64c + lane][b],
     // is kept in registers and advanced by one row of the object cost table
-    // per step (prefetched a step ahead); it never has to be gathered.
+    // per step (prefetched a step ahead); it never has to be gathered.  The
+    // ground-disparity bounds of the next step's base row are prefetched with
+    // it.  Both go through buffer resources: unlike flat loads they do not
+    // hold up the waits on this step's LDS traffic.
     float pcol[NCH], orow[NCH];
+    int thi_n = 0, tlo_n = 0;
     const int nchunk = (nrow + 63) >> 6;             // 64-row chunks of disparity rows
-    auto load_orow = [&](int v) {
+    const auto odf = make_rsrc(in.O_df, (uint32_t)(in.D * in.D) * 4u);
+    const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
+    const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
+    auto load_next = [&](int v) {
+        // object costs of pixel q_v for every disparity row; the bounds of
+        // the base row v+1 (top-down row H-2-v)
         const int qv = in.q[v];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             if (c >= nchunk) break;
             const int i = 64 * c + lane;
-            orow[c] = (qv >= 0 && i < nrow) ? in.O_df[qv * in.D + fbase + i] : 0.0f;
+            orow[c] = (qv >= 0 && i < nrow) ? buf_load(odf, qv * in.D + fbase + i) : 0.0f;
+        }
+        if (v + 1 <= vtop + 1) {
+            thi_n = __builtin_bit_cast(int, buf_load(fgh, H - 2 - v));
+            tlo_n = __builtin_bit_cast(int, buf_load(fgl, H - 2 - v));
         }
     };
 #pragma unroll
     for (int c = 0; c < NCH; ++c) pcol[c] = orow[c] = 0.0f;
-    if (H > 1) load_orow(0);
+    if (H > 1) load_next(0);
 
     // Push-form recurrence: step j finalises row j and folds the stixels
     // that start at b = j+1 into every row k > j.  Row j's costs and prefix
@@ -174,22 +187,19 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             if (c >= nchunk) break;
             pcol[c] += orow[c];                               // PO[.][j+1]
         }
-        if (b < H - 1) load_orow(b);                          // row q_{j+1} for the next step
+        const int thi = thi_n, tlo = tlo_n;                   // bounds at base row b
+        if (b < H - 1) load_next(b);                          // pixel q_{j+1}, base b+1
 
         const float XS =
-            fminf(fminf(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+            vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
         const float Xoo = Co + P.trans[0][0];
         const float Xoo_p = Xoo + P.c_ord;
         const int tord = fp + P.tau_ord;
         const float Xso = Cs + P.trans[2][0];
         float XG = INF, Xgo = INF, Xgo_d = INF, Xgo_g = INF;
-        int thi = 0, tlo = 0;
         if constexpr (GR) {
-            const int r = H - 1 - b;                 // top-down row of the stixel base
-            thi = in.fg_hi[r];
-            tlo = in.fg_lo[r];
             XG = (b <= vtop)
-                ? fminf(fminf(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
+                ? vmin(vmin(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
                 : INF;
             Xgo = Cg + P.trans[1][0];
             Xgo_d = Xgo + P.c_dive;
@@ -204,9 +214,9 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             if constexpr (GR) {
                 float v2 = (f < tlo) ? Xgo_g : Xgo;
                 v2 = (f > thi) ? Xgo_d : v2;
-                pr = fminf(fminf(v1, v2), Xso);
+                pr = vmin(vmin(v1, v2), Xso);
             } else {
-                pr = fminf(v1, Xso);
+                pr = vmin(v1, Xso);
             }
             qtab[64 * c + lane] = pr - pcol[c];
         }
@@ -215,7 +225,11 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         float pk[S], qv[S];
         int fS[S];
         // gathers of a group of slots are in flight together; groups bound
-        // the registers they hold for tall columns
+        // the registers they hold for tall columns.  Slots of a group that
+        // lie past the column's height fold values into rows that are never
+        // read (their gathers stay inside the column's table or read 0 past
+        // its end, and their table index is masked): skipping them one by
+        // one would cost more than the work
         constexpr int G = (S <= 8) ? S : 4;
 #pragma unroll
         for (int g0 = 0; g0 < S; g0 += G) {
@@ -224,7 +238,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
                 if (s < sj) continue;
-                if (s >= nslots) break;
                 const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
                 const uint32_t fi = (uint32_t)(f - fbase);
                 pk[s] = buf_load_b(po, __umul24(fi, stride4) + lane4 + (uint32_t)(s * 256), 0);
@@ -234,7 +247,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
                 if (s < sj) continue;
-                if (s >= nslots) break;
                 const bool act = (s > sj) || (lane > jl);   // rows k > j only
                 float cO = qv[s] + pk[s];
                 float cS = eS[s] + XS;
@@ -243,11 +255,11 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 const bool better = cO < mO[s];
                 mO[s] = better ? cO : mO[s];
                 fO[s] = better ? fS[s] : fO[s];
-                mS[s] = fminf(mS[s], cS);
+                mS[s] = vmin(mS[s], cS);
                 if constexpr (GR) {
                     float cG = eG[s] + XG;
                     cG = act ? cG : INF;
-                    mG[s] = fminf(mG[s], cG);
+                    mG[s] = vmin(mG[s], cG);
                 }
             }
         }

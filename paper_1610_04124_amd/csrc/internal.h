@@ -127,6 +127,13 @@ __device__ __forceinline__ float wave_inclusive_scan(float x) {
     return x;
 }
 
+// IEEE 754-2019 minimum: a single v_minimum3_f32 on gfx950, with no
+// operand canonicalisation (fminf adds one per operand).  The two agree on
+// every value the recurrence produces: no NaN, and no -0.
+__device__ __forceinline__ float vmin(float a, float b) {
+    return __builtin_elementwise_minimum(a, b);
+}
+
 // ------------------------------------------------------------------ Sec. 3.4
 // Rounded mean of a stixel's valid disparities, floor((2S+n)/(2n)), from the
 // prefix differences a = 2S+n and n2 = 2n (both exact integers in FP32).
@@ -141,7 +148,14 @@ __device__ __forceinline__ int rounded_mean(float a, float n2, float eps) {
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+    // base and bytes are the same in every lane; reading them from the first
+    // lane lets the compiler keep the resource in scalar registers (otherwise
+    // each load through it is wrapped in a loop over distinct lane values)
+    const uint64_t p = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    void* ub = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
                                              (int)kBufferWord3);
 }
 
