@@ -23,7 +23,9 @@
 
 using namespace stx;
 
-namespace {
+// A named namespace (not an anonymous one) so that profilers show the
+// kernels by name.
+namespace stx::persist {
 
 struct JobDesc {
     const float* disp;
@@ -65,14 +67,19 @@ __device__ __forceinline__ int wave_max_i(int x) {
 
 __global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
 
+// Waves per SIMD the register allocation of each variant is held to (the
+// compiler's own choice leaves a few registers above the next step down).
+constexpr int batch_waves(int slots) { return slots <= 7 ? 5 : (slots <= 14 ? 3 : 2); }
+
 template <int S, int NCH>
 __global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const JobDesc* __restrict__ jobs,
+__attribute__((amdgpu_waves_per_eu(batch_waves(S)))) void batch_kernel(const JobDesc* __restrict__ jobs,
                                                    const int2* __restrict__ tasks, int ntasks,
                                                    unsigned int* counter, float* scratch,
                                                    long long scratch_stride, int hmax) {
-    __shared__ int16_t qs[kMaxHeight];
-    __shared__ float qtab[kMaxDisparity];
+    __shared__ int16_t qs[64 * S];
+    __shared__ float qtab[256];
+    __shared__ float crow[2 * 64 * S];
     const int lane = threadIdx.x;
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
     (void)hmax;
@@ -188,7 +195,7 @@ __attribute__((amdgpu_waves_per_eu((S <= 8) ? 4 : 2))) void batch_kernel(const J
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
-        solve_column<S, NCH>(H, J.vtop, J.prior, in, out, qtab);
+        solve_column<S, NCH>(H, J.vtop, J.prior, in, out, qtab, crow);
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
 }
@@ -218,7 +225,9 @@ hipError_t launch_batch(int slots, int nch, int grid, hipStream_t st, const JobD
     return hipGetLastError();
 }
 
-}  // namespace
+}  // namespace stx::persist
+
+using namespace stx::persist;
 
 struct stixels_batch {
     stixels_batch_config cfg{};

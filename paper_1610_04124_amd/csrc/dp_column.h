@@ -73,11 +73,12 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
     return c == 0 ? a0 : (c == 1 ? a1 : a2);
 }
 
-// qtab: per-wave LDS scratch of 256 floats.  S: 64-row slots per lane
-// (h <= 64 S); NCH: 64-entry chunks of disparity rows (d_range <= 64 NCH).
+// S: 64-row slots per lane (h <= 64 S); NCH: 64-entry chunks of disparity
+// rows (d_range <= 64 NCH).  Per-wave LDS: qtab[256]; crow[2 * 64 S], the
+// final ground (first half) and sky (second half) cost of every row.
 template <int S, int NCH>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out, float* qtab) {
+                             const ColumnOut& out, float* qtab, float* crow) {
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
@@ -85,12 +86,17 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     const int nrow = fmax - fbase + 1;               // <= d_range <= 64 * NCH
     const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
     const float eps = P.mean_eps;
+    const float cmean = eps - (float)fbase;          // mean_index gives f - fbase
     const float INF = inf_f();
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
+    const auto pgr = make_rsrc(in.PG, (uint32_t)stride4);
+    const auto psr = make_rsrc(in.PS, (uint32_t)stride4);
+    float* const crow_g = crow;             // GR^k of row k, written when row k is reached
+    float* const crow_s = crow + 64 * S;    // SK^k
 
-    float eG[S], eS[S], eA[S], eN[S];   // prefix values at k+1 (ground masked above vtop)
-    float mO[S], mG[S], mS[S];          // OB^k, GR^k, SK^k so far
-    int fO[S];                          // mean of the best object stixel ending at k
+    float eA[S], eN[S];                 // prefix values at k+1 (mean numerator, 2 n)
+    float mO[S];                        // OB^k so far
+    int fO[S];                          // mean (- fbase) of the best object stixel ending at k
 
     // Slots past the column's height (a shorter frame in a batch sized for
     // taller ones) are skipped with wave-uniform branches.
@@ -100,24 +106,19 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         if (s >= nslots) {
-            eG[s] = eS[s] = mO[s] = mG[s] = mS[s] = INF;
+            mO[s] = INF;
             eA[s] = eN[s] = 0.0f;
             fO[s] = 0;
             continue;
         }
         const int k = s * 64 + lane;
         const int kk = min(k + 1, H);
-        const float pg = in.PG[kk], ps = in.PS[kk];
-        eG[s] = (k < H && k <= vtop) ? pg : INF;
-        eS[s] = (k < H) ? ps : INF;
         eA[s] = in.PA[kk];
         eN[s] = in.PN2[kk];
-        const int f = rounded_mean(eA[s], eN[s], eps);
-        mO[s] = buf_load_b(po, __umul24((uint32_t)(f - fbase), stride4) + (uint32_t)kk * 4u, 0) +
+        const int fi = mean_index(eA[s], eN[s], cmean);
+        mO[s] = buf_load_b(po, __umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0) +
                 P.first[0];
-        fO[s] = f;
-        mG[s] = eG[s] + P.first[1];
-        mS[s] = eS[s] + P.first[2];
+        fO[s] = fi;
     }
 
     // The object prefix column at the current base, PO[fbase + 64c + lane][b],
@@ -128,28 +129,43 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // hold up the waits on this step's LDS traffic.
     float pcol[NCH], orow[NCH];
     int thi_n = 0, tlo_n = 0;
+    float ps_n = 0.0f, pg_n = INF;
     const int nchunk = (nrow + 63) >> 6;             // 64-row chunks of disparity rows
     const auto odf = make_rsrc(in.O_df, (uint32_t)(in.D * in.D) * 4u);
     const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
     const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
     auto load_next = [&](int v) {
-        // object costs of pixel q_v for every disparity row; the bounds of
-        // the base row v+1 (top-down row H-2-v)
+        // for step v: object costs of pixel q_v for every disparity row, the
+        // sky and ground prefixes at v+1 (ground INF above vtop) and the
+        // bounds of the base row v+1 (top-down row H-2-v).  Straight-line
+        // code: every index either lies inside its table or falls past the
+        // end of its buffer resource, which reads 0 (v <= H-1 gives
+        // top-down row >= -1; an invalid pixel or a disparity row past the
+        // column's range gives index -1).
         const int qv = in.q[v];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c >= nchunk) break;
             const int i = 64 * c + lane;
-            orow[c] = (qv >= 0 && i < nrow) ? buf_load(odf, qv * in.D + fbase + i) : 0.0f;
+            orow[c] = buf_load(odf, (qv >= 0 && i < nrow) ? qv * in.D + fbase + i : -1);
         }
-        if (v + 1 <= vtop + 1) {
-            thi_n = __builtin_bit_cast(int, buf_load(fgh, H - 2 - v));
-            tlo_n = __builtin_bit_cast(int, buf_load(fgl, H - 2 - v));
-        }
+        ps_n = buf_load(psr, v + 1);
+        const float pg = buf_load(pgr, v + 1);
+        pg_n = (v <= vtop) ? pg : INF;
+        thi_n = __builtin_bit_cast(int, buf_load(fgh, H - 2 - v));
+        tlo_n = __builtin_bit_cast(int, buf_load(fgl, H - 2 - v));
     };
 #pragma unroll
     for (int c = 0; c < NCH; ++c) pcol[c] = orow[c] = 0.0f;
     if (H > 1) load_next(0);
+
+    // The ground and sky data terms of a stixel [b, k] are prefix
+    // differences whose b-side does not depend on k, and their priors depend
+    // on b alone: GR^k = PG[k+1] + min over b <= k of (prior_g(b) - PG[b]),
+    // and the same for SK (Eq. 5).  All values are exact on the cost grid,
+    // so the two minima are kept as running wave-uniform values RG and RS,
+    // and a row's ground and sky costs are written once, when the row is
+    // reached, instead of being folded per row and per step.
+    float RG = P.first[1], RS = P.first[2];
 
     // Push-form recurrence: step j finalises row j and folds the stixels
     // that start at b = j+1 into every row k > j.  Row j's costs and prefix
@@ -167,40 +183,43 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // row j's costs and prefix values, read from its owning lane; the
         // slot is chosen by wave-uniform branches (an indexed choice would
         // put the slot registers in scratch memory)
-        float Co = 0.0f, Cg = 0.0f, Cs = 0.0f, bS = 0.0f, bA = 0.0f, bN = 0.0f, bG = 0.0f;
+        float Co = 0.0f, bA = 0.0f, bN = 0.0f;
         int fp = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (s == sj) {
                 Co = readlane_f(mO[s], jl);
-                Cg = readlane_f(mG[s], jl);
-                Cs = readlane_f(mS[s], jl);
                 fp = readlane_i(fO[s], jl);
-                bS = readlane_f(eS[s], jl);
                 bA = readlane_f(eA[s], jl);
                 bN = readlane_f(eN[s], jl);
-                bG = readlane_f(eG[s], jl);
             }
         }
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            if (c >= nchunk) break;
-            pcol[c] += orow[c];                               // PO[.][j+1]
+        // row j's ground and sky costs (ground is INF above vtop: bG is),
+        // recorded for the backtracking
+        const float bS = ps_n, bG = pg_n;
+        const float Cg = bG + RG, Cs = bS + RS;
+        if (lane == 0) {
+            crow_g[j] = Cg;
+            crow_s[j] = Cs;
         }
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
         const int thi = thi_n, tlo = tlo_n;                   // bounds at base row b
-        if (b < H - 1) load_next(b);                          // pixel q_{j+1}, base b+1
+        load_next(b);                                         // pixel q_{j+1}, base b+1 (b <= H-1)
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+        RS = vmin(RS, XS);
         const float Xoo = Co + P.trans[0][0];
         const float Xoo_p = Xoo + P.c_ord;
-        const int tord = fp + P.tau_ord;
+        const int tord = fp + fbase + P.tau_ord;
         const float Xso = Cs + P.trans[2][0];
         float XG = INF, Xgo = INF, Xgo_d = INF, Xgo_g = INF;
         if constexpr (GR) {
             XG = (b <= vtop)
                 ? vmin(vmin(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
                 : INF;
+            RG = vmin(RG, XG);
             Xgo = Cg + P.trans[1][0];
             Xgo_d = Xgo + P.c_dive;
             Xgo_g = Xgo + P.c_grav;
@@ -238,29 +257,20 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
                 if (s < sj) continue;
-                const int f = rounded_mean(eA[s] - bA, eN[s] - bN, eps);
-                const uint32_t fi = (uint32_t)(f - fbase);
-                pk[s] = buf_load_b(po, __umul24(fi, stride4) + lane4 + (uint32_t)(s * 256), 0);
-                qv[s] = qtab[fi & 255u];
-                fS[s] = f;
+                const uint32_t fi = (uint32_t)mean_index(eA[s] - bA, eN[s] - bN, cmean);
+                pk[s] = buf_load_b(po, __umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
+                qv[s] = qtab[fi & 255u];               // fi < 64 NCH except in rows past H
+                fS[s] = (int)fi;
             }
 #pragma unroll
             for (int s = g0; s < g0 + G && s < S; ++s) {
                 if (s < sj) continue;
                 const bool act = (s > sj) || (lane > jl);   // rows k > j only
                 float cO = qv[s] + pk[s];
-                float cS = eS[s] + XS;
                 cO = act ? cO : INF;
-                cS = act ? cS : INF;
                 const bool better = cO < mO[s];
                 mO[s] = better ? cO : mO[s];
                 fO[s] = better ? fS[s] : fO[s];
-                mS[s] = vmin(mS[s], cS);
-                if constexpr (GR) {
-                    float cG = eG[s] + XG;
-                    cG = act ? cG : INF;
-                    mG[s] = vmin(mG[s], cG);
-                }
             }
         }
         __syncthreads();           // this step's table reads finish before the next step rewrites it
@@ -286,12 +296,19 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         }
     }
 
+    // the top row's ground and sky costs
+    if (lane == 0) {
+        crow_g[H - 1] = ((H - 1 <= vtop) ? buf_load(pgr, H) : INF) + RG;
+        crow_s[H - 1] = buf_load(psr, H) + RS;
+    }
+    __syncthreads();
+
     // ---------------------------------------------------------- backtracking
     const int ktop = H - 1;
     float total = sel_slot<S>(mO, ktop);
     int ctop = 0;
     {
-        const float g = sel_slot<S>(mG, ktop), sk = sel_slot<S>(mS, ktop);
+        const float g = crow_g[ktop], sk = crow_s[ktop];
         if (g < total) { total = g; ctop = 1; }
         if (sk < total) { total = sk; ctop = 2; }
     }
@@ -304,7 +321,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         int k = ktop, cls = ctop, t = 0;
         float target = total;
         while (true) {
-            const float kG = sel_slot<S>(eG, k), kS = sel_slot<S>(eS, k);
+            const float kG = (k <= vtop) ? buf_load(pgr, k + 1) : INF;
+            const float kS = buf_load(psr, k + 1);
             const float kA = sel_slot<S>(eA, k), kN = sel_slot<S>(eN, k);
             const int kk = k + 1;
             int lb = -1, lc = -1, lf = 0;
@@ -342,18 +360,20 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                         // offset: the buffer bounds check turns it into 0
                         data = buf_load(po, (f - fbase) * stride + kk) -
                                buf_load(po, (f - fbase) * stride + bb);
-                        pen_o = (f > fO[s] + P.tau_ord) ? P.c_ord : 0.0f;
+                        pen_o = (f > fO[s] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
                         const int r = inr ? H - 1 - bb : 0;
                         const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
                         pen_g = (f > thi) ? P.c_dive : ((f < tlo) ? P.c_grav : 0.0f);
                     } else if (cls == 1) {
-                        data = kG - eG[s];
+                        // ground stixels end at or below vtop, so PG[bb] is finite
+                        data = kG - buf_load(pgr, bb);
                     } else {
-                        data = kS - eS[s];
+                        data = kS - buf_load(psr, bb);
                     }
+                    const float mg = crow_g[p], ms = crow_s[p];   // p < 64 S
                     const float co = mO[s] + tO + pen_o + data;
-                    const float cg = mG[s] + tG + pen_g + data;
-                    const float cs = mS[s] + tS + data;
+                    const float cg = mg + tG + pen_g + data;
+                    const float cs = ms + tS + data;
                     const int code = !inr ? 3
                                    : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
                     const uint64_t m = __ballot(code < 3);
@@ -362,7 +382,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                         lb = s * 64 + l0 + 1;
                         lc = readlane_i(code, l0);
                         lf = readlane_i(f, l0);
-                        const float pc = (lc == 0) ? mO[s] : ((lc == 1) ? mG[s] : mS[s]);
+                        const float pc = (lc == 0) ? mO[s] : ((lc == 1) ? mg : ms);
                         prevC = readlane_f(pc, l0);
                     }
                 }

@@ -174,8 +174,9 @@ struct DpArgs {
 
 template <int S, int NCH>
 __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
-    __shared__ int16_t qs[kMaxHeight];
-    __shared__ float qtab[kMaxDisparity];
+    __shared__ int16_t qs[64 * S];
+    __shared__ float qtab[256];
+    __shared__ float crow[2 * 64 * S];
     const int col = blockIdx.x;
     const int stride = a.H + 1;
     for (int v = threadIdx.x; v < a.H; v += 64) qs[v] = a.q[(size_t)col * a.H + v];
@@ -199,20 +200,26 @@ __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
     out.total = a.total + col;
     out.overflow = a.overflow + col;
     out.cap = a.cap;
-    solve_column<S, NCH>(a.H, a.vtop, a.prior, in, out, qtab);
+    solve_column<S, NCH>(a.H, a.vtop, a.prior, in, out, qtab, crow);
 }
 
 // ------------------------------------------------------------------ self-test
 __global__ __launch_bounds__(256) void selftest_mean_kernel(int D, float eps,
                                                             unsigned long long* bad) {
-    const int n = blockIdx.x + 1;
+    // block n tests every disparity sum of n valid pixels (n = 0: the empty
+    // stixel), with base 0, base = the mean and base = half the mean
+    const int n = blockIdx.x;
     const long long smax = (long long)n * (D - 1);
     unsigned long long local = 0;
     for (long long S = threadIdx.x; S <= smax; S += 256) {
         const int a = (int)(2 * S + n);
-        const int want = a / (2 * n);
-        const int got = rounded_mean((float)a, (float)(2 * n), eps);
-        local += (got != want) ? 1ull : 0ull;
+        const int want = (n > 0) ? a / (2 * n) : 0;
+        const int bases[3] = {0, want, want / 2};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int got = mean_index((float)a, (float)(2 * n), eps - (float)bases[i]);
+            local += (got != want - bases[i]) ? 1ull : 0ull;
+        }
     }
     if (local) atomicAdd(bad, local);
 }
@@ -305,7 +312,7 @@ hipError_t run_selftest_mean(int D, int max_height, int64_t* mismatches) {
     e = hipMemset(d_bad, 0, sizeof(unsigned long long));
     if (e == hipSuccess) {
         const float eps = (float)ldexp((double)D, -22);
-        hipLaunchKernelGGL(selftest_mean_kernel, dim3(max_height), dim3(256), 0, nullptr, D, eps,
+        hipLaunchKernelGGL(selftest_mean_kernel, dim3(max_height + 1), dim3(256), 0, nullptr, D, eps,
                            d_bad);
         e = hipGetLastError();
     }

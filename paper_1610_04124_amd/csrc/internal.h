@@ -64,6 +64,10 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 __device__ __forceinline__ int readlane_i(int v, int lane) {
     return __builtin_amdgcn_readlane(v, lane);
 }
+// v with lane `lane` replaced by the wave-uniform value x.
+__device__ __forceinline__ float writelane_f(float x, int lane, float v) {
+    return ((int)(threadIdx.x & 63) == lane) ? x : v;
+}
 
 // ------------------------------------------------------------------ Sec. 4.1
 // One reduced pixel from the s disparities of a row strip: lower median (mode
@@ -135,16 +139,28 @@ __device__ __forceinline__ float vmin(float a, float b) {
 }
 
 // ------------------------------------------------------------------ Sec. 3.4
-// Rounded mean of a stixel's valid disparities, floor((2S+n)/(2n)), from the
-// prefix differences a = 2S+n and n2 = 2n (both exact integers in FP32).
-// With r = rcp(n2) (relative error <= 2^-23) and eps = d_range * 2^-22,
+// Rounded mean of a stixel's valid disparities, floor((2S+n)/(2n)), minus a
+// caller-chosen integer base <= the mean, from the prefix differences
+// a = 2S+n and n2 = 2n (both exact integers in FP32); c = eps - base with
+// eps = d_range * 2^-22.  With r = rcp(n2) (relative error <= 2^-23),
 // fma(a, r, eps) lies in [m, m+1) whenever a / n2 lies in [m, m+1) and
 // 2n * d_range < 2^24 / 7, which handle creation enforces (h * d_range <=
-// 2^20).  n = 0 gives a = 0 and f = 0.  The result is >= eps > 0, so
-// truncation is the floor.
+// 2^20); shifting by the integer base keeps the exact value the same
+// distance from the integers and cannot enlarge the rounding error, so the
+// truncation gives m - base.  n = 0 (a = 0): rcp gives +inf, the product
+// NaN, and v_cvt_i32_f32 turns NaN into 0; callers use base 0 whenever a
+// stixel without valid pixels can occur.  stixels_selftest_mean checks all
+// of this on the device.
+__device__ __forceinline__ int cvt_i32_nan0(float x) {
+    int r;
+    asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+__device__ __forceinline__ int mean_index(float a, float n2, float c) {
+    return cvt_i32_nan0(__builtin_fmaf(a, __builtin_amdgcn_rcpf(n2), c));
+}
 __device__ __forceinline__ int rounded_mean(float a, float n2, float eps) {
-    const float r = __builtin_amdgcn_rcpf(fmaxf(n2, 1.0f));
-    return (int)__builtin_fmaf(a, r, eps);
+    return mean_index(a, n2, eps);
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {

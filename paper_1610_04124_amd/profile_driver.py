@@ -6,6 +6,7 @@
 
 batch: the persistent batched launch over 64 synthetic 1024x440 frames
        (stixel width 5), replayed from a HIP graph;
+hires: the same over 16 frames of 2048x880 (stixel width 5, d_range 256);
 frame: the per-frame path (three kernels) on the same frames;
 copy:  a plain 256 MiB device-to-device copy, whose FETCH_SIZE / WRITE_SIZE
        readings calibrate the HBM byte counters.
@@ -24,7 +25,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["batch", "frame", "copy"], default="batch")
+    ap.add_argument("--mode", choices=["batch", "hires", "frame", "copy"], default="batch")
     ap.add_argument("--launches", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
     args = ap.parse_args()
@@ -45,16 +46,22 @@ def main():
     import synth
     import paper_1610_04124_amd as P
 
-    W, H = 1024, 440
-    params = synth.make_params()
+    if args.mode == "hires":
+        W, H, D, nframes = 2048, 880, 256, min(args.frames, 16)
+        cam = synth.camera_for_size(W, H)
+        params = synth.make_params(camera=cam, max_width=W, max_height=H, max_disparity=D)
+        specs = [synth.SceneSpec(W, H, D, cam, seed=i) for i in range(nframes)]
+    else:
+        W, H, D, nframes = 1024, 440, 128, args.frames
+        params = synth.make_params()
+        specs = [synth.SceneSpec(seed=i) for i in range(nframes)]
     h = P.Stixels(params)
-    frames = [torch.from_numpy(synth.generate_frame(synth.SceneSpec(seed=i))).to(dev)
-              for i in range(args.frames)]
+    frames = [torch.from_numpy(synth.generate_frame(sp)).to(dev) for sp in specs]
     outs = [h.new_output(W, H) for _ in frames]
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    if args.mode == "batch":
-        b = P.Batch(len(frames), len(frames) * (W // 5), H, 128)
+    if args.mode in ("batch", "hires"):
+        b = P.Batch(len(frames), len(frames) * (W // 5), H, D)
         b.capture(list(zip([h] * len(frames), frames, outs)), stream)
         for _ in range(args.launches):
             b.replay(stream)
