@@ -45,9 +45,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles():
+def traffic_from_profiles(kernel):
     """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary, if it was taken on the current kernel sources."""
+    summary, if it was taken on the current kernel sources and on the same
+    kernel variant."""
     path = os.path.join(ROOT, "profiles", "batch_kernel_1024x440_b64_traffic.json")
     if not os.path.exists(path):
         return None
@@ -55,7 +56,7 @@ def traffic_from_profiles():
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -84,7 +85,7 @@ def cpu_baseline(frames, params, n_frames):
                       f"C FP64 oracle, OpenMP over columns, {dt:.2f} s wall"}
 
 
-def hires(warmup, steps):
+def hires(warmup, steps, tune_launch=True):
     """16 frames of 2048x880 (d_range 256) at stixel widths 3 and 5, one
     batched graph replay per step."""
     import torch
@@ -106,7 +107,12 @@ def hires(warmup, steps):
         outs = [h.new_output(Wh, Hh) for _ in frames]
         b = P.Batch(16, 16 * (Wh // s), Hh, 256)
         torch.cuda.synchronize()
-        b.capture(list(zip([h] * 16, frames, outs)), stream)
+        items = list(zip([h] * 16, frames, outs))
+        if tune_launch:
+            from paper_1610_04124_amd.autotune import tune
+            tuned = tune(b, items, stream, cache_path=None)
+        else:
+            b.capture(items, stream)
         for _ in range(warmup):
             b.replay(stream)
         torch.cuda.synchronize()
@@ -116,8 +122,10 @@ def hires(warmup, steps):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         pairs = 16 * (Wh // s) * Hh * (Hh + 1) // 2
+        g, _ = b.info()
         out[f"s{s}"] = {"fps": round(16 / dt, 2), "ms_per_batch": round(dt * 1e3, 4),
-                        "valu_frac": round(OPS_PER_PAIR * pairs / dt / VALU_PEAK, 4)}
+                        "valu_frac": round(OPS_PER_PAIR * pairs / dt / VALU_PEAK, 4),
+                        "waves_per_column": b.waves(), "workgroups": g}
     return out
 
 
@@ -196,6 +204,7 @@ def main():
         from paper_1610_04124_amd.autotune import tune
         tuned = tune(batch, items, stream, cache_path=None)
     grid, ntasks = batch.info()
+    waves = batch.waves()
     for _ in range(args.warmup):
         batch.replay(stream)
     torch.cuda.synchronize()
@@ -215,6 +224,11 @@ def main():
     avg_launch_s = statistics.mean(launch_ms) * 1e-3
 
     # ---------------- per-frame path: three kernels per frame, one stream
+    frame_tuned = None
+    if not args.no_tune:
+        from paper_1610_04124_amd.autotune import tune_frame
+        frame_tuned = tune_frame(h, d_frames[0], outs[0], stream)
+    frame_waves = h.waves(W, H)
     for i in range(FRAMES):
         h.compute(d_frames[i], outs[i], stream)
     torch.cuda.synchronize()
@@ -238,10 +252,11 @@ def main():
     # ---------------- roofline of the persistent kernel
     ops = OPS_PER_PAIR * pairs_per_frame() * FRAMES
     achieved = ops / avg_launch_s
-    traffic = traffic_from_profiles()
+    kernel = f"batch_kernel<7, 2, {waves}>"
+    traffic = traffic_from_profiles(kernel)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK / 1e12, 4),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
-                "kernel": "batch_kernel<7>", "ops_per_launch": ops,
+                "kernel": kernel, "ops_per_launch": ops,
                 "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
 
     result = {
@@ -253,11 +268,11 @@ def main():
                    "height": H, "stixel_width": S_WIDTH, "max_disparity": D_RANGE,
                    "columns_per_frame": W // S_WIDTH,
                    "path": "persistent batched launch replayed from a HIP graph",
-                   "workgroups": grid, "tasks": ntasks},
+                   "workgroups": grid, "tasks": ntasks, "waves_per_column": waves},
         "batched": {"fps": round(batched_fps, 2),
                     "batch_latency_ms_p50": round(percentile(launch_ms, 0.5), 4),
                     "batch_latency_ms_p99": round(percentile(launch_ms, 0.99), 4)},
-        "per_frame": {"fps": round(per_frame_fps, 2),
+        "per_frame": {"fps": round(per_frame_fps, 2), "waves_per_column": frame_waves,
                       "frame_latency_ms_p50": round(percentile(lat, 0.5), 4),
                       "frame_latency_ms_p99": round(percentile(lat, 0.99), 4)},
         "roofline": roofline,
@@ -265,7 +280,9 @@ def main():
     }
     if tuned is not None:
         result["config"]["autotune_tried_ms"] = tuned["tried"]
-    result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5))
+    if frame_tuned is not None:
+        result["per_frame"]["autotune_tried_ms"] = frame_tuned["tried"]
+    result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5), not args.no_tune)
     if args.serve_seconds > 0:
         result["serving"] = serve(args.serve_seconds)
         # the same cameras at 16x the rate: continuous batching under load

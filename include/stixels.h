@@ -142,6 +142,19 @@ int stixels_output_capacity(const stixels_handle *h, int32_t height, int32_t *ca
 int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, int32_t height,
                     void *stream, const stixels_output *out);
 
+/* Wavefronts per column of the recurrence in stixels_compute (Sec. 4.3
+ * assigns one thread block per column; here a column's rows are shared by
+ * 1, 2 or 4 wave64s, interleaved by 64-row slot).  0 (the default) picks
+ * automatically from the frame's column count and the device's compute
+ * units; a request is capped by the rows: 4 needs more than 192 rows, 2
+ * more than 64.  Results do not depend on it.  STIXELS_E_INVALID_ARG for
+ * other values. */
+int stixels_set_waves(stixels_handle *h, int32_t waves);
+
+/* Waves per column that stixels_compute uses for a frame of this size under
+ * the current setting (0 for a null handle or a size below the minimum). */
+int stixels_get_waves(const stixels_handle *h, int32_t height, int32_t width);
+
 /* Text of the last error reported on this handle ("" if none); with NULL,
  * the reason the last stixels_create or stixels_host_table of this thread
  * failed. */
@@ -196,6 +209,15 @@ int stixels_batch_replay(stixels_batch *b, void *stream);
  * device keeps resident and the batch's scratch allows); used by the
  * autotuner.  Takes effect at the next compute or capture. */
 int stixels_batch_set_workgroups(stixels_batch *b, int32_t workgroups);
+
+/* Wavefronts per column of later calls (as in stixels_set_waves: 1, 2 or
+ * 4, capped by the batch's row slots; 0 = 1); used by the autotuner.
+ * Results do not depend on it.  Takes effect at the next compute or
+ * capture. */
+int stixels_batch_set_waves(stixels_batch *b, int32_t waves);
+
+/* Waves per column of the last compute or capture (0 before the first). */
+int stixels_batch_waves(const stixels_batch *b);
 
 /* Workgroups of the persistent launch last used, and the number of
  * tasks (frame columns) of the last call. */

@@ -1,13 +1,19 @@
-"""Autotuner of the persistent batched launch.
+"""Autotuner of the batched launch and of the per-frame path.
 
-The tunable is the number of resident single-wave workgroups of the
-persistent kernel.  More workgroups hide more latency; fewer leave each
-SIMD less contended and shorten the tail when the column tasks do not divide
-evenly into the resident set.  For a job list the tuner captures the launch
-once per candidate, times a few graph replays with HIP events, keeps the
-fastest, and caches the choice on disk keyed by the device and the job
-signature (the multiset of frame height, width, stixel width and d_range).
-Results never depend on the choice: every candidate computes the same bits.
+Batched launch: two tunables.  Waves per column (1, 2 or 4 wave64s share a
+column's rows): more waves shorten each column and, with fewer columns in
+flight, shrink the set of object prefix tables the caches have to hold, at
+the price of one barrier per recurrence step.  Resident workgroups of the
+persistent kernel: more hide more latency; fewer leave each SIMD less
+contended and shorten the tail when the column tasks do not divide evenly
+into the resident set.  For a job list the tuner captures the launch once
+per candidate, times a few graph replays with HIP events, keeps the fastest,
+and caches the choice on disk keyed by the device and the job signature
+(the multiset of frame height, width, stixel width and d_range).
+
+Per-frame path: waves per column, timed the same way on one frame.
+
+Results never depend on the choices: every candidate computes the same bits.
 """
 
 from __future__ import annotations
@@ -62,45 +68,75 @@ def candidates(max_workgroups: int, ntasks: int):
     return sorted(g for g in out if g <= max_workgroups)
 
 
-def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAULT_CACHE,
-         force: bool = False) -> dict:
-    """Pick and apply the workgroup count for `items` on `batch`; returns the
-    record (also cached).  Leaves the batch captured with the chosen grid."""
+def _time(run, stream, replays):
     import torch
+    run()                                          # warm
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(replays):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        run()
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    return statistics.median(ms)
 
+
+WAVES = (1, 2, 4)
+
+
+def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAULT_CACHE,
+         force: bool = False, waves=WAVES) -> dict:
+    """Pick and apply waves per column and the workgroup count for `items`
+    on `batch`; returns the record (also cached).  Leaves the batch captured
+    with the chosen configuration."""
     key = device_key() + "||" + signature(items)
     cache = _load(cache_path) if cache_path else {}
-    if not force and key in cache:
+    if not force and key in cache and "waves" in cache[key]:
         rec = cache[key]
+        batch.set_waves(rec["waves"])
         batch.set_workgroups(rec["workgroups"])
         batch.capture(items, stream)
         return dict(rec, cached=True)
 
-    batch.set_workgroups(0)
-    batch.capture(items, stream)
-    gmax, ntasks = batch.info()
     timings = {}
-    for g in candidates(gmax, ntasks):
-        batch.set_workgroups(g)
+    ntasks = 0
+    for w in waves:
+        batch.set_waves(w)
+        batch.set_workgroups(0)
         batch.capture(items, stream)
-        batch.replay(stream)                      # warm
-        torch.cuda.synchronize()
-        ms = []
-        for _ in range(replays):
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            batch.replay(stream)
-            b.record(stream)
-            b.synchronize()
-            ms.append(a.elapsed_time(b))
-        timings[g] = statistics.median(ms)
+        if batch.waves() != w:
+            continue                               # capped by the row slots
+        gmax, ntasks = batch.info()
+        for g in candidates(gmax, ntasks):
+            batch.set_workgroups(g)
+            batch.capture(items, stream)
+            timings[(w, g)] = _time(lambda: batch.replay(stream), stream, replays)
     best = min(timings, key=timings.get)
-    batch.set_workgroups(best)
+    batch.set_waves(best[0])
+    batch.set_workgroups(best[1])
     batch.capture(items, stream)
-    rec = {"workgroups": best, "ms": timings[best], "tasks": ntasks, "max_workgroups": gmax,
-           "tried": {str(k): round(v, 4) for k, v in sorted(timings.items())}}
+    rec = {"waves": best[0], "workgroups": best[1], "ms": timings[best], "tasks": ntasks,
+           "tried": {f"w{w}/g{g}": round(v, 4) for (w, g), v in sorted(timings.items())}}
     if cache_path:
         cache[key] = rec
         _store(cache_path, cache)
     return dict(rec, cached=False)
+
+
+def tune_frame(handle, disp, out, stream, replays: int = 5, waves=WAVES) -> dict:
+    """Pick and apply waves per column of the per-frame path for frames of
+    this size; returns the timings."""
+    H, W = disp.shape
+    timings = {}
+    for w in waves:
+        handle.set_waves(w)
+        if handle.waves(W, H) != w:
+            continue
+        timings[w] = _time(lambda: handle.compute(disp, out, stream), stream, replays)
+    best = min(timings, key=timings.get)
+    handle.set_waves(best)
+    return {"waves": best, "ms": timings[best],
+            "tried": {f"w{w}": round(v, 4) for w, v in sorted(timings.items())}}

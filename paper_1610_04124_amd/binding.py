@@ -27,7 +27,8 @@ EXPORTS = (
     "stixels_compute", "stixels_last_error", "stixels_status_string",
     "stixels_batch_create", "stixels_batch_destroy", "stixels_batch_compute",
     "stixels_batch_capture", "stixels_batch_replay", "stixels_batch_info",
-    "stixels_batch_set_workgroups",
+    "stixels_batch_set_workgroups", "stixels_batch_set_waves", "stixels_batch_waves",
+    "stixels_set_waves", "stixels_get_waves",
     "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
     "stixels_debug_stage", "stixels_selftest_mean",
 )
@@ -115,6 +116,10 @@ def lib():
         L.stixels_batch_replay.argtypes = [vp, vp]
         L.stixels_batch_info.argtypes = [vp, P(i32), P(i32)]
         L.stixels_batch_set_workgroups.argtypes = [vp, i32]
+        L.stixels_batch_set_waves.argtypes = [vp, i32]
+        L.stixels_batch_waves.argtypes = [vp]
+        L.stixels_set_waves.argtypes = [vp, i32]
+        L.stixels_get_waves.argtypes = [vp, i32, i32]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
         _lib = L
@@ -242,6 +247,16 @@ class Stixels:
         if rc != OK:
             self._err(rc, "stixels_output_capacity")
         return n.value
+
+    def set_waves(self, waves: int) -> None:
+        """Wavefronts per column of the recurrence (1, 2, 4; 0 = automatic)."""
+        rc = lib().stixels_set_waves(self.h, int(waves))
+        if rc != OK:
+            self._err(rc, "stixels_set_waves")
+
+    def waves(self, width: int, height: int) -> int:
+        """Wavefronts per column that compute uses for a frame of this size."""
+        return int(lib().stixels_get_waves(self.h, int(height), int(width)))
 
     def new_output(self, width: int, height: int, device=None) -> FrameOutput:
         import torch
@@ -390,6 +405,16 @@ class Batch:
         rc = lib().stixels_batch_replay(self.b, _stream_ptr(stream))
         if rc != OK:
             self._err(rc, "stixels_batch_replay")
+
+    def set_waves(self, waves: int):
+        """Wavefronts per column of later launches (1, 2, 4; 0 = 1)."""
+        rc = lib().stixels_batch_set_waves(self.b, int(waves))
+        if rc != OK:
+            self._err(rc, "stixels_batch_set_waves")
+
+    def waves(self) -> int:
+        """Wavefronts per column of the last launch."""
+        return int(lib().stixels_batch_waves(self.b))
 
     def set_workgroups(self, n: int):
         rc = lib().stixels_batch_set_workgroups(self.b, int(n))

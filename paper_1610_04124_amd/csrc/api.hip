@@ -212,6 +212,10 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     rc = build_tables(h);
     if (rc == STIXELS_OK && hipGetDevice(&h->device) != hipSuccess)
         rc = fail(h, STIXELS_E_HIP, "no HIP device");
+    if (rc == STIXELS_OK &&
+        hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
+            hipSuccess)
+        rc = fail(h, STIXELS_E_HIP, "cannot read the compute unit count");
     if (rc == STIXELS_OK) rc = upload(h, &h->d_sky, h->sky);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_ground, h->ground);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_object_t, h->object_t);
@@ -275,12 +279,26 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
                    out->overflow, out->capacity};
     hipError_t e = launch_reduce(m, d_disparity, width, height, ncols, ws.q, st);
     if (e == hipSuccess) e = launch_tables(m, ws, height, ncols, vtop, st);
-    if (e == hipSuccess) e = launch_dp(m, ws, height, ncols, vtop, fo, st);
+    const int waves = frame_waves(h->waves, height, ncols, h->num_cu);
+    if (e == hipSuccess) e = launch_dp(m, ws, height, ncols, vtop, waves, fo, st);
     if (e != hipSuccess)
         return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     h->last_W = width;
     h->last_H = height;
     return STIXELS_OK;
+}
+
+int stixels_set_waves(stixels_handle* h, int32_t waves) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4)
+        return fail(h, STIXELS_E_INVALID_ARG, "waves per column must be 0, 1, 2 or 4");
+    h->waves = waves;
+    return STIXELS_OK;
+}
+
+int stixels_get_waves(const stixels_handle* h, int32_t height, int32_t width) {
+    if (!h || height < 1 || width < h->s) return 0;
+    return frame_waves(h->waves, height, width / h->s, h->num_cu);
 }
 
 const char* stixels_last_error(const stixels_handle* h) {

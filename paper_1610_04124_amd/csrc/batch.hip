@@ -68,25 +68,36 @@ __device__ __forceinline__ int wave_max_i(int x) {
 __global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
 
 // Waves per SIMD the register allocation of each variant is held to (the
-// compiler's own choice leaves a few registers above the next step down).
-constexpr int batch_waves(int slots) { return slots <= 7 ? 5 : (slots <= 14 ? 3 : 2); }
+// compiler's own choice leaves a few registers above the next step down;
+// multi-wave workgroups keep a little more room for the row broadcast).
+constexpr int batch_waves(int slots_per_wave, int waves) {
+    return slots_per_wave <= 7 ? (waves == 1 ? 5 : 4) : (slots_per_wave <= 14 ? 3 : 2);
+}
 
-template <int S, int NCH>
-__global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(batch_waves(S)))) void batch_kernel(const JobDesc* __restrict__ jobs,
-                                                   const int2* __restrict__ tasks, int ntasks,
-                                                   unsigned int* counter, float* scratch,
-                                                   long long scratch_stride, int hmax) {
+// One workgroup of W waves per column task.
+template <int S, int NCH, int W>
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch_kernel(
+    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
+    unsigned int* counter, float* scratch, long long scratch_stride, int hmax) {
     __shared__ int16_t qs[64 * S];
-    __shared__ float qtab[256];
-    __shared__ float crow[2 * 64 * S];
-    const int lane = threadIdx.x;
+    __shared__ ColumnLds<S, W> lds;
+    __shared__ int task_slot;
+    __shared__ int red[3][W];
+    const int lane = threadIdx.x & 63;
+    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
     (void)hmax;
     for (;;) {
         int t = 0;
-        if (lane == 0) t = (int)atomicAdd(counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
+        if constexpr (W == 1) {
+            if (lane == 0) t = (int)atomicAdd(counter, 1u);
+            t = __builtin_amdgcn_readfirstlane(t);
+        } else {
+            if (threadIdx.x == 0) task_slot = (int)atomicAdd(counter, 1u);
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(task_slot);
+        }
         if (t >= ntasks) break;
         const int2 tk = tasks[t];
         const JobDesc& J = jobs[tk.x];
@@ -95,71 +106,87 @@ __attribute__((amdgpu_waves_per_eu(batch_waves(S)))) void batch_kernel(const Job
         // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
         int lmin = INT_MAX, lmax = -1;
         bool inv = false;
-        for (int base = 0; base < H; base += 64) {
-            const int v = base + lane;
-            if (v < H) {
-                const int r = H - 1 - v;
-                const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
-                                         J.reduce_mode, D);
-                qs[v] = (int16_t)x;
-                if (x >= 0) {
-                    lmin = min(lmin, x);
-                    lmax = max(lmax, x);
-                } else {
-                    inv = true;
-                }
+        for (int v = threadIdx.x; v < H; v += 64 * W) {
+            const int r = H - 1 - v;
+            const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
+                                     J.reduce_mode, D);
+            qs[v] = (int16_t)x;
+            if (x >= 0) {
+                lmin = min(lmin, x);
+                lmax = max(lmax, x);
+            } else {
+                inv = true;
             }
         }
         // object means lie in [smallest, largest valid q]; a stixel without
         // valid pixels has mean 0, so the table starts at 0 when the column
         // holds an invalid pixel
-        int fmin = __ballot(inv) ? 0 : wave_min_i(lmin);
+        int anyinv = __ballot(inv) ? 1 : 0;
+        int fmin = wave_min_i(lmin);
         int fmax = wave_max_i(lmax);
+        if constexpr (W > 1) {
+            if (lane == 0) {
+                red[0][wave] = fmin;
+                red[1][wave] = fmax;
+                red[2][wave] = anyinv;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                fmin = min(fmin, red[0][w]);
+                fmax = max(fmax, red[1][w]);
+                anyinv |= red[2][w];
+            }
+        }
+        if (anyinv) fmin = 0;
         if (fmax < 0) {
             fmin = 0;
             fmax = 0;
         }
         __syncthreads();
 
-        // Sec. 4.2: prefix tables into the scratch slot
+        // Sec. 4.2: prefix tables into the scratch slot: the four small ones
+        // by wave 0, the object rows f = fmin + wave, fmin + wave + W, ...
         float* PG = ws;
         float* PS = ws + stride;
         float* PA = ws + 2 * stride;
         float* PN = ws + 3 * stride;
         float* PO = ws + 4 * stride;
-        if (lane == 0) {
-            PG[0] = 0.0f;
-            PS[0] = 0.0f;
-            PA[0] = 0.0f;
-            PN[0] = 0.0f;
-        }
-        float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
-        for (int base = 0; base < H; base += 64) {
-            const int v = base + lane;
-            const int x = (v < H) ? (int)qs[v] : -1;
-            float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
-            if (x >= 0) {
-                g = J.ground[(size_t)(H - 1 - v) * D + x];
-                sk = J.sky[x];
-                aa = (float)(2 * x + 1);
-                nn = 2.0f;
+        if (wave == 0) {
+            if (lane == 0) {
+                PG[0] = 0.0f;
+                PS[0] = 0.0f;
+                PA[0] = 0.0f;
+                PN[0] = 0.0f;
             }
-            g = wave_inclusive_scan(g) + cg;
-            sk = wave_inclusive_scan(sk) + cs;
-            aa = wave_inclusive_scan(aa) + ca;
-            nn = wave_inclusive_scan(nn) + cn;
-            if (v < H) {
-                PG[v + 1] = g;
-                PS[v + 1] = sk;
-                PA[v + 1] = aa;
-                PN[v + 1] = nn;
+            float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+            for (int base = 0; base < H; base += 64) {
+                const int v = base + lane;
+                const int x = (v < H) ? (int)qs[v] : -1;
+                float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+                if (x >= 0) {
+                    g = J.ground[(size_t)(H - 1 - v) * D + x];
+                    sk = J.sky[x];
+                    aa = (float)(2 * x + 1);
+                    nn = 2.0f;
+                }
+                g = wave_inclusive_scan(g) + cg;
+                sk = wave_inclusive_scan(sk) + cs;
+                aa = wave_inclusive_scan(aa) + ca;
+                nn = wave_inclusive_scan(nn) + cn;
+                if (v < H) {
+                    PG[v + 1] = g;
+                    PS[v + 1] = sk;
+                    PA[v + 1] = aa;
+                    PN[v + 1] = nn;
+                }
+                cg = readlane_f(g, 63);
+                cs = readlane_f(sk, 63);
+                ca = readlane_f(aa, 63);
+                cn = readlane_f(nn, 63);
             }
-            cg = readlane_f(g, 63);
-            cs = readlane_f(sk, 63);
-            ca = readlane_f(aa, 63);
-            cn = readlane_f(nn, 63);
         }
-        for (int f = fmin; f <= fmax; ++f) {
+        for (int f = fmin + wave; f <= fmax; f += W) {
             const float* orow = J.object_t + (size_t)f * D;
             float* prow = PO + (size_t)(f - fmin) * stride;
             if (lane == 0) prow[0] = 0.0f;
@@ -173,7 +200,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves(S)))) void batch_kernel(const Job
                 carry = readlane_f(o, 63);
             }
         }
-        __syncthreads();   // the tables written above are read back below
+        __syncthreads();   // the tables written above are read back below, by every wave
 
         // Sec. 4.3-4.4
         ColumnIn in;
@@ -195,29 +222,29 @@ __attribute__((amdgpu_waves_per_eu(batch_waves(S)))) void batch_kernel(const Job
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
-        solve_column<S, NCH>(H, J.vtop, J.prior, in, out, qtab, crow);
+        solve_column<S, NCH, W>(H, J.vtop, J.prior, in, out, lds);
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
 }
 
-void* batch_kernel_for(int slots, int nch) {
-#define STX_CASE(n, c) \
-    if (slots == n && nch == c) return reinterpret_cast<void*>(&batch_kernel<n, c>);
+void* batch_kernel_for(int slots, int nch, int waves) {
+#define STX_CASE(n, c, w) \
+    if (slots == n && nch == c && waves == w) return reinterpret_cast<void*>(&batch_kernel<n, c, w>);
     STX_FOR_EACH_VARIANT(STX_CASE)
 #undef STX_CASE
     return nullptr;
 }
 
-hipError_t launch_batch(int slots, int nch, int grid, hipStream_t st, const JobDesc* jobs,
-                        const int2* tasks, int ntasks, unsigned int* counter, float* scratch,
-                        long long stride, int hmax) {
+hipError_t launch_batch(int slots, int nch, int waves, int grid, hipStream_t st,
+                        const JobDesc* jobs, const int2* tasks, int ntasks, unsigned int* counter,
+                        float* scratch, long long stride, int hmax) {
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
     bool launched = false;
-#define STX_CASE(n, c)                                                                   \
-    if (slots == n && nch == c) {                                                        \
-        hipLaunchKernelGGL((batch_kernel<n, c>), dim3(grid), dim3(64), 0, st, jobs, tasks, \
-                           ntasks, counter, scratch, stride, hmax);                      \
-        launched = true;                                                                 \
+#define STX_CASE(n, c, w)                                                                    \
+    if (slots == n && nch == c && waves == w) {                                              \
+        hipLaunchKernelGGL((batch_kernel<n, c, w>), dim3(grid), dim3(64 * w), 0, st, jobs,   \
+                           tasks, ntasks, counter, scratch, stride, hmax);                   \
+        launched = true;                                                                     \
     }
     STX_FOR_EACH_VARIANT(STX_CASE)
 #undef STX_CASE
@@ -247,7 +274,8 @@ struct stixels_batch {
     bool staged_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int last_grid = 0, last_tasks = 0;
+    int waves = 1;          // requested waves per column
+    int last_grid = 0, last_tasks = 0, last_waves = 0;
     std::string err;
 };
 
@@ -258,10 +286,17 @@ int bfail(stixels_batch* b, int code, const std::string& m) {
     return code;
 }
 
-int occupancy_grid(stixels_batch* b, int slots, int nch, int* grid) {
+// Waves per column for a launch of this slot count: the request, capped so
+// that every wave owns at least one 64-row slot.
+int batch_waves_for(const stixels_batch* b, int slots) {
+    const int cap = slots >= 4 ? 4 : (slots >= 2 ? 2 : 1);
+    return std::min(std::max(b->waves, 1), cap);
+}
+
+int occupancy_grid(stixels_batch* b, int slots, int nch, int waves, int* grid) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots, nch), 64, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots, nch, waves),
+                                                     64 * waves, 0) != hipSuccess ||
         per_cu < 1)
         return bfail(b, STIXELS_E_HIP, "occupancy query failed");
     *grid = per_cu * b->num_cu;
@@ -341,9 +376,10 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     return STIXELS_OK;
 }
 
-int choose_grid(stixels_batch* b, int slots, int nch, long long stride, int ntasks, int* grid) {
+int choose_grid(stixels_batch* b, int slots, int nch, int waves, long long stride, int ntasks,
+                int* grid) {
     int g = 0;
-    int rc = occupancy_grid(b, slots, nch, &g);
+    int rc = occupancy_grid(b, slots, nch, waves, &g);
     if (rc != STIXELS_OK) return rc;
     if (b->cfg.workgroups > 0) g = std::min(g, (int)b->cfg.workgroups);
     const long long by_scratch = (long long)(b->scratch_floats / (size_t)stride);
@@ -395,7 +431,9 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
         rc = STIXELS_E_HIP;
     int grid = 0;
     const int slots = kernel_slots(cfg->max_height);
-    if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, kernel_chunks(cfg->max_disparity), &grid);
+    // one-wave workgroups are the most that can be resident: the scratch
+    // slots cover them, and so every later choice of waves per column
+    if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, kernel_chunks(cfg->max_disparity), 1, &grid);
     if (rc == STIXELS_OK && cfg->workgroups > 0) grid = std::min(grid, (int)cfg->workgroups);
     if (rc == STIXELS_OK) {
         b->scratch_floats = (size_t)grid * (size_t)(4 + cfg->max_disparity) *
@@ -444,17 +482,19 @@ int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
     int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, stride, ntasks, &grid);
+    const int waves = batch_waves_for(b, slots);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
-    const hipError_t e = launch_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
+    const hipError_t e = launch_batch(slots, nch, waves, grid, st, b->d_jobs, b->d_tasks, ntasks,
                                       b->d_counter, b->d_scratch, stride, hmax);
     if (e != hipSuccess)
         return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
     b->last_grid = grid;
     b->last_tasks = ntasks;
+    b->last_waves = waves;
     return STIXELS_OK;
 }
 
@@ -465,7 +505,8 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
     int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, stride, ntasks, &grid);
+    const int waves = batch_waves_for(b, slots);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     // the graph reads its own descriptor copy, uploaded once here
@@ -477,8 +518,8 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     destroy_graph(b);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
-    const hipError_t e = launch_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
-                                      b->d_counter_g, b->d_scratch, stride, hmax);
+    const hipError_t e = launch_batch(slots, nch, waves, grid, st, b->d_jobs_g, b->d_tasks_g,
+                                      ntasks, b->d_counter_g, b->d_scratch, stride, hmax);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -492,6 +533,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     }
     b->last_grid = grid;
     b->last_tasks = ntasks;
+    b->last_waves = waves;
     return STIXELS_OK;
 }
 
@@ -508,6 +550,15 @@ int stixels_batch_set_workgroups(stixels_batch* b, int32_t workgroups) {
     b->cfg.workgroups = workgroups;
     return STIXELS_OK;
 }
+
+int stixels_batch_set_waves(stixels_batch* b, int32_t waves) {
+    if (!b || (waves != 0 && waves != 1 && waves != 2 && waves != 4))
+        return bfail(b, STIXELS_E_INVALID_ARG, "waves per column must be 0, 1, 2 or 4");
+    b->waves = waves == 0 ? 1 : waves;
+    return STIXELS_OK;
+}
+
+int stixels_batch_waves(const stixels_batch* b) { return b ? b->last_waves : 0; }
 
 int stixels_batch_info(const stixels_batch* b, int32_t* workgroups, int32_t* tasks) {
     if (!b) return STIXELS_E_INVALID_ARG;

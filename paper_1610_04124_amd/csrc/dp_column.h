@@ -1,14 +1,18 @@
 // dp_column.h -- the Eq. 5-6 recurrence and backtracking for one column, run
-// by one wave64.
+// by W wave64s (W = 1, 2 or 4).
 //
-// Work distribution (gfx950): lane l owns the rows k = 64*s + l for slots
-// s < S, with its running minima OB^k, GR^k, SK^k, the mean of the best
-// object stixel ending at k, and the prefix values at k+1 held in VGPRs.  The
-// recurrence is evaluated in push form: once row j is final (all candidates
-// with a cut at b <= j have been seen), its costs are broadcast from the
-// owning lane with v_readlane and every lane folds the candidates that start
-// at b = j+1 into its rows k > j.  There is no barrier, no LDS and no
-// cross-lane reduction per step, unlike the one-thread-per-k CTA of Sec. 4.3.
+// Work distribution (gfx950): the rows are cut into 64-row slots s < S; slot
+// s belongs to wave s mod W (interleaved, so that the waves keep an even
+// share of the rows still open as the recurrence advances), and lane l of
+// that wave owns row k = 64 s + l, with its running minimum OB^k, the mean of
+// the best object stixel ending at k and the prefix values at k+1 in VGPRs.
+// The recurrence is evaluated in push form: once row j is final (all
+// candidates with a cut at b <= j have been seen), its values are read from
+// the owning lane with v_readlane (and, with W > 1, passed to the other
+// waves through LDS behind one barrier per step) and every lane folds the
+// candidates that start at b = j+1 into its rows k > j.  There is no
+// cross-lane reduction per step, unlike the one-thread-per-k CTA of
+// Sec. 4.3.
 //
 // The index table of Sec. 3.3 is not stored.  Because every cost is exact on
 // the grid, backtracking recovers each link by recomputing the candidates of
@@ -38,6 +42,17 @@ struct ColumnIn {
     const int32_t* fg_lo;   // gravity threshold per top-down image row
 };
 
+// Per-workgroup LDS of one column (S slots, W waves).
+template <int S, int W>
+struct ColumnLds {
+    float qtab[W][256];     // per wave: prior minus PO[f][b] over the disparity rows
+    float crow_g[64 * S];   // final GR^k of every row
+    float crow_s[64 * S];   // final SK^k
+    float crow_o[64 * S];   // final OB^k
+    uint8_t crow_f[64 * S]; // mean - fbase of the best object stixel ending at k
+    float bc[2][4];         // row j's values for the other waves (double-buffered)
+};
+
 struct ColumnOut {
     int32_t* count;
     uint32_t* rec;          // capacity records of 3 dwords (stixels_record)
@@ -45,15 +60,6 @@ struct ColumnOut {
     uint8_t* overflow;
     int cap;
 };
-
-template <int S>
-__device__ __forceinline__ float sel_slot(const float (&a)[S], int k) {
-    float v = 0.0f;
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        if ((k >> 6) == s) v = readlane_f(a[s], k & 63);
-    return v;
-}
 
 // Emitted stixel, kept by lane t (t-th stixel found from the top).
 struct RecRegs {
@@ -73,13 +79,16 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
     return c == 0 ? a0 : (c == 1 ? a1 : a2);
 }
 
-// S: 64-row slots per lane (h <= 64 S); NCH: 64-entry chunks of disparity
-// rows (d_range <= 64 NCH).  Per-wave LDS: qtab[256]; crow[2 * 64 S], the
-// final ground (first half) and sky (second half) cost of every row.
-template <int S, int NCH>
+// S: 64-row slots (h <= 64 S); NCH: 64-entry chunks of disparity rows
+// (d_range <= 64 NCH); W: waves per column (the workgroup is 64 W lanes, all
+// of which call this function).  On return the results are written.
+template <int S, int NCH, int W>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out, float* qtab, float* crow) {
+                             const ColumnOut& out, ColumnLds<S, W>& L) {
+    static_assert(W == 1 || W == 2 || W == 4, "waves per column");
+    constexpr int SW = (S + W - 1) / W;              // slots per wave
     const int lane = threadIdx.x & 63;
+    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
     const int fbase = in.fbase, fmax = in.fmax;
@@ -89,44 +98,48 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     const float cmean = eps - (float)fbase;          // mean_index gives f - fbase
     const float INF = inf_f();
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
-    const auto pgr = make_rsrc(in.PG, (uint32_t)stride4);
-    const auto psr = make_rsrc(in.PS, (uint32_t)stride4);
-    float* const crow_g = crow;             // GR^k of row k, written when row k is reached
-    float* const crow_s = crow + 64 * S;    // SK^k
+    const auto pgr = make_rsrc(in.PG, stride4);
+    const auto psr = make_rsrc(in.PS, stride4);
+    const auto par = make_rsrc(in.PA, stride4);
+    const auto pnr = make_rsrc(in.PN2, stride4);
+    float* const qtab = L.qtab[wave];
 
-    float eA[S], eN[S];                 // prefix values at k+1 (mean numerator, 2 n)
-    float mO[S];                        // OB^k so far
-    int fO[S];                          // mean (- fbase) of the best object stixel ending at k
+    // local slot t of this wave is global slot t W + wave
+    float eA[SW], eN[SW];               // prefix values at k+1 (mean numerator, 2 n)
+    float mO[SW];                       // OB^k so far
+    int fO[SW];                         // mean (- fbase) of the best object stixel ending at k
 
     // Slots past the column's height (a shorter frame in a batch sized for
-    // taller ones) are skipped with wave-uniform branches.
+    // taller ones, or the last slot of a wave when W does not divide S) are
+    // padding: their rows are never read.
     const int nslots = (H + 63) >> 6;
 
     // Bottom-stixel candidates (b = 0): data(0, k) + F[c] + beta.
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int t = 0; t < SW; ++t) {
+        const int s = t * W + wave;
         if (s >= nslots) {
-            mO[s] = INF;
-            eA[s] = eN[s] = 0.0f;
-            fO[s] = 0;
+            mO[t] = INF;
+            eA[t] = eN[t] = 0.0f;
+            fO[t] = 0;
             continue;
         }
         const int k = s * 64 + lane;
         const int kk = min(k + 1, H);
-        eA[s] = in.PA[kk];
-        eN[s] = in.PN2[kk];
-        const int fi = mean_index(eA[s], eN[s], cmean);
-        mO[s] = buf_load_b(po, __umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0) +
+        eA[t] = in.PA[kk];
+        eN[t] = in.PN2[kk];
+        const int fi = mean_index(eA[t], eN[t], cmean);
+        mO[t] = buf_load_b(po, __umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0) +
                 P.first[0];
-        fO[s] = fi;
+        fO[t] = fi;
     }
 
     // The object prefix column at the current base, PO[fbase + 64c + lane][b],
     // is kept in registers and advanced by one row of the object cost table
     // per step (prefetched a step ahead); it never has to be gathered.  The
-    // ground-disparity bounds of the next step's base row are prefetched with
-    // it.  Both go through buffer resources: unlike flat loads they do not
-    // hold up the waits on this step's LDS traffic.
+    // sky and ground prefixes and the ground-disparity bounds of the next
+    // step are prefetched with it.  All go through buffer resources: unlike
+    // flat loads they do not hold up the waits on this step's LDS traffic.
     float pcol[NCH], orow[NCH];
     int thi_n = 0, tlo_n = 0;
     float ps_n = 0.0f, pg_n = INF;
@@ -168,39 +181,59 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     float RG = P.first[1], RS = P.first[2];
 
     // Push-form recurrence: step j finalises row j and folds the stixels
-    // that start at b = j+1 into every row k > j.  Row j's costs and prefix
-    // values are broadcast from the lane that owns row j.  Per step, the prior
-    // of an object stixel with mean f (min over the three predecessor
-    // classes, with the ordering / diving / gravity penalties) minus
-    // PO[f][b] is tabulated once over the column's disparity rows in LDS; a
-    // candidate is then that entry plus one gathered PO[f][k+1].  All slots'
-    // gathers are issued before any candidate is folded.  Steps where no
-    // ground stixel can end at or below b-1 (b > vtop+1) skip the ground
-    // terms.  Slots below the current row are skipped by uniform branches.
+    // that start at b = j+1 into every row k > j.  Per step, the prior of an
+    // object stixel with mean f (min over the three predecessor classes,
+    // with the ordering / diving / gravity penalties) minus PO[f][b] is
+    // tabulated once over the column's disparity rows in LDS; a candidate is
+    // then that entry plus one gathered PO[f][k+1].  All slots' gathers are
+    // issued before any candidate is folded.  Steps where no ground stixel
+    // can end at or below b-1 (b > vtop+1) skip the ground terms.  Slots
+    // below the current row are skipped by uniform branches.
     auto step = [&](auto gr_tag, const int sj, const int jl) {
         constexpr bool GR = decltype(gr_tag)::value;
         const int j = sj * 64 + jl, b = j + 1;
-        // row j's costs and prefix values, read from its owning lane; the
-        // slot is chosen by wave-uniform branches (an indexed choice would
-        // put the slot registers in scratch memory)
+        // row j's object cost, mean and prefix values, read from its owning
+        // lane; the slot is chosen by wave-uniform branches (an indexed
+        // choice would put the slot registers in scratch memory)
         float Co = 0.0f, bA = 0.0f, bN = 0.0f;
         int fp = 0;
+        auto read_row = [&]() {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s == sj) {
-                Co = readlane_f(mO[s], jl);
-                fp = readlane_i(fO[s], jl);
-                bA = readlane_f(eA[s], jl);
-                bN = readlane_f(eN[s], jl);
+            for (int t = 0; t < SW; ++t) {
+                if (t == sj / W) {
+                    Co = readlane_f(mO[t], jl);
+                    fp = readlane_i(fO[t], jl);
+                    bA = readlane_f(eA[t], jl);
+                    bN = readlane_f(eN[t], jl);
+                }
             }
+        };
+        if constexpr (W == 1) {
+            read_row();
+        } else {
+            float* bc = L.bc[j & 1];
+            if (wave == sj % W) {
+                read_row();
+                if (lane == 0) {
+                    bc[0] = Co;
+                    bc[1] = __builtin_bit_cast(float, fp);
+                    bc[2] = bA;
+                    bc[3] = bN;
+                }
+            }
+            __syncthreads();
+            Co = bc[0];
+            fp = __builtin_bit_cast(int, bc[1]);
+            bA = bc[2];
+            bN = bc[3];
         }
         // row j's ground and sky costs (ground is INF above vtop: bG is),
         // recorded for the backtracking
         const float bS = ps_n, bG = pg_n;
         const float Cg = bG + RG, Cs = bS + RS;
-        if (lane == 0) {
-            crow_g[j] = Cg;
-            crow_s[j] = Cs;
+        if (wave == 0 && lane == 0) {
+            L.crow_g[j] = Cg;
+            L.crow_s[j] = Cs;
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
@@ -224,6 +257,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             Xgo_d = Xgo + P.c_dive;
             Xgo_g = Xgo + P.c_grav;
         }
+        // this wave's copy of the table (LDS accesses of one wave complete
+        // in order, so no barrier guards it)
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             if (c >= nchunk) break;
@@ -239,46 +274,47 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             }
             qtab[64 * c + lane] = pr - pcol[c];
         }
-        __syncthreads();
 
-        float pk[S], qv[S];
-        int fS[S];
+        float pk[SW], qv[SW];
+        int fS[SW];
         // gathers of a group of slots are in flight together; groups bound
         // the registers they hold for tall columns.  Slots of a group that
         // lie past the column's height fold values into rows that are never
         // read (their gathers stay inside the column's table or read 0 past
         // its end, and their table index is masked): skipping them one by
         // one would cost more than the work
-        constexpr int G = (S <= 8) ? S : 4;
+        constexpr int G = (SW <= 8) ? SW : 4;
 #pragma unroll
-        for (int g0 = 0; g0 < S; g0 += G) {
-            if (g0 >= nslots) break;
-            if (g0 + G <= sj) continue;
+        for (int g0 = 0; g0 < SW; g0 += G) {
+            if (g0 * W >= nslots) break;
+            if ((g0 + G - 1) * W + wave < sj) continue;
 #pragma unroll
-            for (int s = g0; s < g0 + G && s < S; ++s) {
+            for (int t = g0; t < g0 + G && t < SW; ++t) {
+                const int s = t * W + wave;
                 if (s < sj) continue;
-                const uint32_t fi = (uint32_t)mean_index(eA[s] - bA, eN[s] - bN, cmean);
-                pk[s] = buf_load_b(po, __umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
-                qv[s] = qtab[fi & 255u];               // fi < 64 NCH except in rows past H
-                fS[s] = (int)fi;
+                const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
+                pk[t] = buf_load_b(po, __umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
+                qv[t] = qtab[fi & 255u];               // fi < 64 NCH except in rows past H
+                fS[t] = (int)fi;
             }
 #pragma unroll
-            for (int s = g0; s < g0 + G && s < S; ++s) {
+            for (int t = g0; t < g0 + G && t < SW; ++t) {
+                const int s = t * W + wave;
                 if (s < sj) continue;
                 const bool act = (s > sj) || (lane > jl);   // rows k > j only
-                float cO = qv[s] + pk[s];
+                float cO = qv[t] + pk[t];
                 cO = act ? cO : INF;
-                const bool better = cO < mO[s];
-                mO[s] = better ? cO : mO[s];
-                fO[s] = better ? fS[s] : fO[s];
+                const bool better = cO < mO[t];
+                mO[t] = better ? cO : mO[t];
+                fO[t] = better ? fS[t] : fO[t];
             }
         }
-        __syncthreads();           // this step's table reads finish before the next step rewrites it
     };
 
     if constexpr (S <= 8) {
         // unrolled over the slot of row j, so that every slot test above is
-        // decided at compile time and the slots' gathers share one block
+        // decided at compile time (for W = 1) and the slots' gathers share
+        // one block
 #pragma unroll
         for (int sj = 0; sj < S; ++sj) {
             const int jend = min(64, H - 1 - sj * 64);
@@ -296,19 +332,31 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         }
     }
 
-    // the top row's ground and sky costs
-    if (lane == 0) {
-        crow_g[H - 1] = ((H - 1 <= vtop) ? buf_load(pgr, H) : INF) + RG;
-        crow_s[H - 1] = buf_load(psr, H) + RS;
+    // the top row's ground and sky costs, and every row's object cost and
+    // mean, into LDS for the backtracking
+    if (wave == 0 && lane == 0) {
+        L.crow_g[H - 1] = ((H - 1 <= vtop) ? buf_load(pgr, H) : INF) + RG;
+        L.crow_s[H - 1] = buf_load(psr, H) + RS;
+    }
+#pragma unroll
+    for (int t = 0; t < SW; ++t) {
+        const int s = t * W + wave;
+        if (s < S) {
+            L.crow_o[s * 64 + lane] = mO[t];
+            L.crow_f[s * 64 + lane] = (uint8_t)fO[t];
+        }
     }
     __syncthreads();
+    if (wave != 0) return;
 
     // ---------------------------------------------------------- backtracking
+    // (wave 0; every row's final costs are in LDS, its prefix values in the
+    // column's tables)
     const int ktop = H - 1;
-    float total = sel_slot<S>(mO, ktop);
+    float total = L.crow_o[ktop];
     int ctop = 0;
     {
-        const float g = crow_g[ktop], sk = crow_s[ktop];
+        const float g = L.crow_g[ktop], sk = L.crow_s[ktop];
         if (g < total) { total = g; ctop = 1; }
         if (sk < total) { total = sk; ctop = 2; }
     }
@@ -323,7 +371,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         while (true) {
             const float kG = (k <= vtop) ? buf_load(pgr, k + 1) : INF;
             const float kS = buf_load(psr, k + 1);
-            const float kA = sel_slot<S>(eA, k), kN = sel_slot<S>(eN, k);
+            const float kA = buf_load(par, k + 1), kN = buf_load(pnr, k + 1);
             const int kk = k + 1;
             int lb = -1, lc = -1, lf = 0;
             float prevC = 0.0f;
@@ -345,46 +393,44 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                     lf = f0;
                 }
             }
-#pragma unroll
             for (int s = 0; s < S; ++s) {
-                if (lb < 0 && s * 64 < k) {
-                    const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
-                    const bool inr = p < k;
-                    const int bb = p + 1;
-                    float data;
-                    int f = 0;
-                    float pen_o = 0.0f, pen_g = 0.0f;
-                    if (cls == 0) {
-                        f = rounded_mean(kA - eA[s], kN - eN[s], eps);
-                        // lanes past the row (!inr) may form a negative row
-                        // offset: the buffer bounds check turns it into 0
-                        data = buf_load(po, (f - fbase) * stride + kk) -
-                               buf_load(po, (f - fbase) * stride + bb);
-                        pen_o = (f > fO[s] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
-                        const int r = inr ? H - 1 - bb : 0;
-                        const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
-                        pen_g = (f > thi) ? P.c_dive : ((f < tlo) ? P.c_grav : 0.0f);
-                    } else if (cls == 1) {
-                        // ground stixels end at or below vtop, so PG[bb] is finite
-                        data = kG - buf_load(pgr, bb);
-                    } else {
-                        data = kS - buf_load(psr, bb);
-                    }
-                    const float mg = crow_g[p], ms = crow_s[p];   // p < 64 S
-                    const float co = mO[s] + tO + pen_o + data;
-                    const float cg = mg + tG + pen_g + data;
-                    const float cs = ms + tS + data;
-                    const int code = !inr ? 3
-                                   : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
-                    const uint64_t m = __ballot(code < 3);
-                    if (m) {
-                        const int l0 = (int)__builtin_ctzll(m);
-                        lb = s * 64 + l0 + 1;
-                        lc = readlane_i(code, l0);
-                        lf = readlane_i(f, l0);
-                        const float pc = (lc == 0) ? mO[s] : ((lc == 1) ? mg : ms);
-                        prevC = readlane_f(pc, l0);
-                    }
+                if (lb >= 0 || s * 64 >= k) break;
+                const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
+                const bool inr = p < k;
+                const int bb = p + 1;
+                float data;
+                int f = 0;
+                float pen_o = 0.0f, pen_g = 0.0f;
+                const float mo = L.crow_o[p], mg = L.crow_g[p], ms = L.crow_s[p];   // p < 64 S
+                if (cls == 0) {
+                    // lanes past the row (!inr) may form out-of-range
+                    // indices: the buffer bounds checks turn them into 0
+                    f = rounded_mean(kA - buf_load(par, bb), kN - buf_load(pnr, bb), eps);
+                    data = buf_load(po, (f - fbase) * stride + kk) -
+                           buf_load(po, (f - fbase) * stride + bb);
+                    pen_o = (f > (int)L.crow_f[p] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
+                    const int r = inr ? H - 1 - bb : 0;
+                    const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
+                    pen_g = (f > thi) ? P.c_dive : ((f < tlo) ? P.c_grav : 0.0f);
+                } else if (cls == 1) {
+                    // ground stixels end at or below vtop, so PG[bb] is finite
+                    data = kG - buf_load(pgr, bb);
+                } else {
+                    data = kS - buf_load(psr, bb);
+                }
+                const float co = mo + tO + pen_o + data;
+                const float cg = mg + tG + pen_g + data;
+                const float cs = ms + tS + data;
+                const int code = !inr ? 3
+                               : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
+                const uint64_t m = __ballot(code < 3);
+                if (m) {
+                    const int l0 = (int)__builtin_ctzll(m);
+                    lb = s * 64 + l0 + 1;
+                    lc = readlane_i(code, l0);
+                    lf = readlane_i(f, l0);
+                    const float pc = (lc == 0) ? mo : ((lc == 1) ? mg : ms);
+                    prevC = readlane_f(pc, l0);
                 }
             }
             if (lb < 0) return -1;

@@ -7,9 +7,11 @@
 //                       own disparity range, with DPP wave scans;
 //   dp      (Sec. 4.3-4.4)  the recurrence and backtracking, one wave64 per
 //                       column (dp_column.h).
+#include <algorithm>
 #include <climits>
 
 #include "dp_column.h"
+
 #include "launch.h"
 
 namespace stx {
@@ -172,14 +174,14 @@ struct DpArgs {
     Prior prior;
 };
 
-template <int S, int NCH>
-__global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
+// One workgroup of W waves per column.
+template <int S, int NCH, int W>
+__global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
     __shared__ int16_t qs[64 * S];
-    __shared__ float qtab[256];
-    __shared__ float crow[2 * 64 * S];
+    __shared__ ColumnLds<S, W> lds;
     const int col = blockIdx.x;
     const int stride = a.H + 1;
-    for (int v = threadIdx.x; v < a.H; v += 64) qs[v] = a.q[(size_t)col * a.H + v];
+    for (int v = threadIdx.x; v < a.H; v += 64 * W) qs[v] = a.q[(size_t)col * a.H + v];
     __syncthreads();
     ColumnIn in;
     in.PG = a.prefix + ((size_t)0 * a.ncols + col) * stride;
@@ -200,7 +202,7 @@ __global__ __launch_bounds__(64) void dp_kernel(DpArgs a) {
     out.total = a.total + col;
     out.overflow = a.overflow + col;
     out.cap = a.cap;
-    solve_column<S, NCH>(a.H, a.vtop, a.prior, in, out, qtab, crow);
+    solve_column<S, NCH, W>(a.H, a.vtop, a.prior, in, out, lds);
 }
 
 // ------------------------------------------------------------------ self-test
@@ -271,8 +273,19 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
     return hipGetLastError();
 }
 
+int frame_waves(int requested, int H, int ncols, int num_cu) {
+    const int slots = kernel_slots(H);
+    if (requested > 0) return std::min(requested, slots >= 4 ? 4 : (slots >= 2 ? 2 : 1));
+    // automatic: the most waves per column that keep the frame within about
+    // two waves per SIMD
+    for (int w : {4, 2}) {
+        if (w <= slots && (long long)ncols * w <= 8LL * num_cu) return w;
+    }
+    return 1;
+}
+
 hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
-                     const FrameOutput& out, hipStream_t st) {
+                     int waves, const FrameOutput& out, hipStream_t st) {
     DpArgs a;
     a.q = ws.q;
     a.object_df = m.object_df;
@@ -292,11 +305,11 @@ hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int 
     a.vtop = vtop;
     a.prior = m.prior;
     const int slots = kernel_slots(H), nch = kernel_chunks(m.D);
-    const dim3 g(ncols), b(64);
+    const dim3 g(ncols), b(64 * waves);
     bool launched = false;
-#define STX_CASE(n, c)                                                  \
-    if (slots == n && nch == c) {                                       \
-        hipLaunchKernelGGL((dp_kernel<n, c>), g, b, 0, st, a);          \
+#define STX_CASE(n, c, w)                                               \
+    if (slots == n && nch == c && waves == w) {                         \
+        hipLaunchKernelGGL((dp_kernel<n, c, w>), g, b, 0, st, a);       \
         launched = true;                                                \
     }
     STX_FOR_EACH_VARIANT(STX_CASE)

@@ -12,6 +12,8 @@ struct stixels_handle {
     stixels_params p;
     int D = 0, Hmax = 0, Wmax = 0, s = 0, ncols_max = 0;
     int device = 0;
+    int num_cu = 0;
+    int waves = 0;          // waves per column of the recurrence (0 = automatic)
     // host copies of the rounded tables
     std::vector<float> sky, ground, object_t, object_df;
     std::vector<int32_t> fg_hi, fg_lo;

@@ -35,10 +35,17 @@ __host__ __device__ constexpr int kernel_slots(int h) {
 // 64-entry disparity chunks for a d_range.
 __host__ __device__ constexpr int kernel_chunks(int d_range) { return d_range <= 128 ? 2 : 4; }
 
-#define STX_FOR_EACH_VARIANT(X)                                                              \
-    X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2) X(10, 2) X(12, 2)     \
-    X(14, 2) X(16, 2) X(1, 4) X(2, 4) X(3, 4) X(4, 4) X(5, 4) X(6, 4) X(7, 4) X(8, 4)     \
-    X(10, 4) X(12, 4) X(14, 4) X(16, 4)
+// Instantiated (slots, disparity chunks, waves per column) triples.
+#define STX_FOR_EACH_VARIANT(X) \
+    X(1, 2, 1) X(2, 2, 1) X(2, 2, 2) X(3, 2, 1) X(3, 2, 2) X(4, 2, 1) X(4, 2, 2) X(4, 2, 4) \
+    X(5, 2, 1) X(5, 2, 2) X(5, 2, 4) X(6, 2, 1) X(6, 2, 2) X(6, 2, 4) X(7, 2, 1) X(7, 2, 2) \
+    X(7, 2, 4) X(8, 2, 1) X(8, 2, 2) X(8, 2, 4) X(10, 2, 1) X(10, 2, 2) X(10, 2, 4) \
+    X(12, 2, 1) X(12, 2, 2) X(12, 2, 4) X(14, 2, 1) X(14, 2, 2) X(14, 2, 4) X(16, 2, 1) \
+    X(16, 2, 2) X(16, 2, 4) X(1, 4, 1) X(2, 4, 1) X(2, 4, 2) X(3, 4, 1) X(3, 4, 2) \
+    X(4, 4, 1) X(4, 4, 2) X(4, 4, 4) X(5, 4, 1) X(5, 4, 2) X(5, 4, 4) X(6, 4, 1) X(6, 4, 2) \
+    X(6, 4, 4) X(7, 4, 1) X(7, 4, 2) X(7, 4, 4) X(8, 4, 1) X(8, 4, 2) X(8, 4, 4) X(10, 4, 1) \
+    X(10, 4, 2) X(10, 4, 4) X(12, 4, 1) X(12, 4, 2) X(12, 4, 4) X(14, 4, 1) X(14, 4, 2) \
+    X(14, 4, 4) X(16, 4, 1) X(16, 4, 2) X(16, 4, 4)
 
 // Quantised prior constants of one camera model, in FP32 (exact on the grid).
 struct Prior {

@@ -44,8 +44,11 @@ hipError_t launch_reduce(const DeviceModel& m, const float* disp, int W, int H, 
                          int16_t* q, hipStream_t st);
 hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols,
                          int vtop, hipStream_t st);
+// Waves per column of the per-frame recurrence: `requested` (1, 2 or 4,
+// capped by the slot count) or, for 0, an automatic choice.
+int frame_waves(int requested, int H, int ncols, int num_cu);
 hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
-                     const FrameOutput& out, hipStream_t st);
+                     int waves, const FrameOutput& out, hipStream_t st);
 hipError_t run_selftest_mean(int D, int max_height, int64_t* mismatches);
 
 // Bottom-up row limit of ground stixels for a frame of height H (FP64, the

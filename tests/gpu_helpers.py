@@ -28,11 +28,17 @@ def to_device(a: np.ndarray):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device())
 
 
-def gpu_frame(handle: P.Stixels, disp: np.ndarray, capacity: int | None = None) -> dict:
+def gpu_frame(handle: P.Stixels, disp: np.ndarray, capacity: int | None = None,
+              waves: int | None = None) -> dict:
+    """One frame through stixels_compute; `waves` sets the wavefronts per
+    column first (and must be honoured for the frame's height)."""
     import torch
     H, W = disp.shape
     cap = capacity if capacity else handle.capacity(H)
     out = P.FrameOutput(handle.num_columns(W), cap, device())
+    if waves is not None:
+        handle.set_waves(waves)
+        assert handle.waves(W, H) == waves, (waves, handle.waves(W, H))
     handle.compute(to_device(disp), out)
     torch.cuda.synchronize()
     return out.to_host()

@@ -21,12 +21,14 @@ def frame_setup(n, seeds=None):
     return p, h, frames
 
 
-def run_batch(items, workgroups=0, max_h=440, max_d=128):
+def run_batch(items, workgroups=0, max_h=440, max_d=128, waves=1):
     import torch
     b = P.Batch(len(items), sum(h.num_columns(d.shape[1]) for h, d, _ in items), max_h, max_d,
                 workgroups)
+    b.set_waves(waves)
     b.compute(items)
     torch.cuda.synchronize()
+    assert b.waves() == waves
     return b
 
 
@@ -47,6 +49,20 @@ def test_batch64_matches_oracle_and_per_frame():
         assert_frames_equal(outs[i].to_host(), gpu_frame(h, f), f"batch vs per-frame {i}")
 
 
+@pytest.mark.parametrize("waves", [2, 4])
+def test_batch_waves_match_per_frame(waves):
+    """16 frames of 1024x440 with several wavefronts per column: bitwise
+    equal to the one-wave per-frame path."""
+    announce(f"batch 16 x 1024x440 waves={waves}")
+    p, h, frames = frame_setup(16)
+    outs = [h.new_output(1024, 440) for _ in frames]
+    items = [(h, to_device(f), o) for f, o in zip(frames, outs)]
+    run_batch(items, waves=waves)
+    for i, f in enumerate(frames):
+        assert_frames_equal(outs[i].to_host(), gpu_frame(h, f, waves=1), f"waves {waves} frame {i}")
+    assert_frames_equal(outs[3].to_host(), oracle.frame(p, frames[3]), "oracle frame 3")
+
+
 def uneven_items(n):
     """Frames of the uneven workload: four sizes, stixel widths 3/5/7, their
     own cameras and disparity ranges, one handle per frame."""
@@ -62,11 +78,11 @@ def uneven_items(n):
     return items, refs
 
 
-@pytest.mark.parametrize("workgroups", [0, 7])
-def test_uneven_batch_matches_oracle(workgroups):
-    announce(f"uneven batch workgroups={workgroups}")
+@pytest.mark.parametrize("workgroups,waves", [(0, 1), (7, 1), (0, 2), (5, 4)])
+def test_uneven_batch_matches_oracle(workgroups, waves):
+    announce(f"uneven batch workgroups={workgroups} waves={waves}")
     items, refs = uneven_items(10)
-    run_batch(items, workgroups, max_h=880, max_d=256)
+    run_batch(items, workgroups, max_h=880, max_d=256, waves=waves)
     for i, ((h, d, out), (p, disp)) in enumerate(zip(items, refs)):
         assert_frames_equal(out.to_host(), oracle.frame(p, disp), f"uneven frame {i}")
 

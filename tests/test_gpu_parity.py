@@ -139,33 +139,64 @@ def test_frame_parity_perturbed_models(mi):
     assert_frames_equal(gpu_frame(h, disp), oracle.frame(p, disp), f"model {mi}")
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_frame_parity_1024x440(seed):
-    """The paper's headline frame: 1024x440, stixel width 5, 204 columns."""
-    announce(f"1024x440 seed={seed}")
+@pytest.mark.parametrize("seed,waves", [(0, 1), (1, 2), (2, 4), (0, 4)])
+def test_frame_parity_1024x440(seed, waves):
+    """The paper's headline frame: 1024x440, stixel width 5, 204 columns,
+    with 1, 2 and 4 wavefronts per column."""
+    announce(f"1024x440 seed={seed} waves={waves}")
     p, h = handle_for(1024, 440)
     disp = synth.generate_frame(synth.SceneSpec(seed=seed))
-    assert_frames_equal(gpu_frame(h, disp), oracle.frame(p, disp), f"1024x440 seed {seed}")
+    assert_frames_equal(gpu_frame(h, disp, waves=waves), oracle.frame(p, disp),
+                        f"1024x440 seed {seed} waves {waves}")
 
 
-@pytest.mark.parametrize("s", [3, 5])
-def test_frame_parity_2048x880(s):
-    """High resolution: 880 rows (14 row slots per lane), d_range 256."""
-    announce(f"2048x880 s={s}")
+def multiwave_cases():
+    """Heights around the 64-row slot boundaries and slot counts that the
+    waves do not divide (the last wave holds a padding slot)."""
+    cases = []
+    rng = np.random.default_rng(77)
+    for H in (65, 127, 128, 129, 191, 193, 250, 257, 320, 449, 513, 700):
+        for waves in (2, 4):
+            if waves == 4 and H <= 192:
+                continue
+            s = int(rng.choice([1, 3, 5, 7]))
+            W = int(s * rng.integers(2, 30) + rng.integers(0, s))
+            D = int(rng.choice([64, 128, 256]))
+            cases.append((W, H, s, D, waves, int(rng.integers(1 << 30))))
+    return cases
+
+
+@pytest.mark.parametrize("W,H,s,D,waves,seed", multiwave_cases())
+def test_frame_parity_multiwave(W, H, s, D, waves, seed):
+    announce(f"multiwave W={W} H={H} s={s} D={D} waves={waves} seed={seed}")
+    cam = dict(synth.CAMERA_1024x440, horizon_row=float(seed % H))
+    p, h = handle_for(W, H, s=s, D=D, camera=cam)
+    disp = synth.random_columns_frame(seed, W, H, D)
+    assert_frames_equal(gpu_frame(h, disp, waves=waves), oracle.frame(p, disp),
+                        f"multiwave {W}x{H} waves {waves}")
+
+
+@pytest.mark.parametrize("s,waves", [(3, 1), (5, 2), (5, 4)])
+def test_frame_parity_2048x880(s, waves):
+    """High resolution: 880 rows (14 row slots), d_range 256."""
+    announce(f"2048x880 s={s} waves={waves}")
     W, H = 2048, 880
     cam = synth.camera_for_size(W, H)
     p, h = handle_for(W, H, s=s, D=256, camera=cam)
     disp = synth.generate_frame(synth.SceneSpec(W, H, 256, cam, seed=s))
-    assert_frames_equal(gpu_frame(h, disp), oracle.frame(p, disp), f"2048x880 s={s}")
+    assert_frames_equal(gpu_frame(h, disp, waves=waves), oracle.frame(p, disp),
+                        f"2048x880 s={s} waves={waves}")
 
 
-def test_frame_parity_max_height():
+@pytest.mark.parametrize("waves", [1, 4])
+def test_frame_parity_max_height(waves):
     """h = 1024, the largest height a handle accepts (16 row slots)."""
-    announce("max height 1024")
+    announce(f"max height 1024 waves={waves}")
     W, H = 45, 1024
     p, h = handle_for(W, H, s=5, D=128, camera=dict(synth.CAMERA_1024x440, horizon_row=400.0))
     disp = synth.random_columns_frame(11, W, H, 128)
-    assert_frames_equal(gpu_frame(h, disp), oracle.frame(p, disp), "h=1024")
+    assert_frames_equal(gpu_frame(h, disp, waves=waves), oracle.frame(p, disp),
+                        f"h=1024 waves {waves}")
 
 
 def test_many_stixels_per_column():
@@ -181,6 +212,8 @@ def test_many_stixels_per_column():
     ref = oracle.frame(p, disp)
     assert ref["counts"].max() > 64
     assert_frames_equal(gpu_frame(h, disp), ref, "many stixels")
+    assert_frames_equal(gpu_frame(h, disp, waves=4), ref, "many stixels, 4 waves")
+    h.set_waves(0)
     for cap in (1, 7, 100):
         assert_frames_equal(gpu_frame(h, disp, capacity=cap), oracle.frame(p, disp, cap=cap),
                             f"many stixels cap {cap}")
@@ -215,6 +248,22 @@ def test_deterministic_and_reusable():
     for k in ("counts", "total", "overflow"):
         assert np.array_equal(a[k], b[k])
     assert np.array_equal(a["records"], b["records"])
+
+
+def test_waves_setting():
+    announce("waves setting")
+    p, h = handle_for(1024, 440)
+    for w in (1, 2, 4):
+        h.set_waves(w)
+        assert h.waves(1024, 440) == w
+        assert h.waves(1024, 100) == min(w, 2)      # 2 row slots
+        assert h.waves(1024, 64) == 1
+    h.set_waves(0)
+    assert h.waves(1024, 440) in (1, 2, 4)
+    for bad in (3, 5, -1, 8):
+        with pytest.raises(B.StixelsError) as ei:
+            h.set_waves(bad)
+        assert ei.value.code == B.E_INVALID_ARG
 
 
 def test_errors_leave_outputs_untouched():
