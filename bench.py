@@ -31,7 +31,12 @@ sys.path.insert(0, ROOT)
 METRIC = "stixel frames/s @1024×440 w=5 (batched vs per-frame); p50/p99 frame latency"
 W, H, S_WIDTH, D_RANGE, FRAMES = 1024, 440, 5, 128, 64
 VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
-OPS_PER_PAIR = 13
+# Essential lane-ops per (cut, row) pair of the recurrence: the object
+# candidate's mean (two prefix differences, reciprocal-multiply, round),
+# its data term (one prefix difference), the prior add and the min.  The
+# ground and sky minima are separable (a running minimum per column step),
+# so they add O(h) per column, not work per pair.
+OPS_PER_PAIR = 7
 
 
 def pairs_per_frame(W=W, H=H, s=S_WIDTH):
@@ -273,6 +278,8 @@ def main():
                     "batch_latency_ms_p50": round(percentile(launch_ms, 0.5), 4),
                     "batch_latency_ms_p99": round(percentile(launch_ms, 0.99), 4)},
         "per_frame": {"fps": round(per_frame_fps, 2), "waves_per_column": frame_waves,
+                      "po_placement": (None if frame_tuned is None else
+                                       ("lds" if frame_tuned["po_placement"] == 2 else "hbm")),
                       "frame_latency_ms_p50": round(percentile(lat, 0.5), 4),
                       "frame_latency_ms_p99": round(percentile(lat, 0.99), 4)},
         "roofline": roofline,

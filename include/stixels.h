@@ -155,6 +155,14 @@ int stixels_set_waves(stixels_handle *h, int32_t waves);
  * the current setting (0 for a null handle or a size below the minimum). */
 int stixels_get_waves(const stixels_handle *h, int32_t height, int32_t width);
 
+/* Placement of a column's object prefix table (Sec. 4.2 keeps LUT_object in
+ * global memory) for the recurrence of stixels_compute: 1 = read from
+ * global memory (HBM and the caches); 2 = copied into the workgroup's LDS
+ * when the column's table (its disparity rows x (height+1) floats) fits,
+ * else global memory; 0 (the default) = as 2 for heights up to 512, as 1
+ * above.  Results do not depend on it.  STIXELS_E_INVALID_ARG otherwise. */
+int stixels_set_po_placement(stixels_handle *h, int32_t placement);
+
 /* Text of the last error reported on this handle ("" if none); with NULL,
  * the reason the last stixels_create or stixels_host_table of this thread
  * failed. */

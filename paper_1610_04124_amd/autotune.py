@@ -11,7 +11,9 @@ per candidate, times a few graph replays with HIP events, keeps the fastest,
 and caches the choice on disk keyed by the device and the job signature
 (the multiset of frame height, width, stixel width and d_range).
 
-Per-frame path: waves per column, timed the same way on one frame.
+Per-frame path: waves per column and the placement of the object prefix
+table (global memory, or an LDS copy per column where it fits), timed the
+same way on one frame.
 
 Results never depend on the choices: every candidate computes the same bits.
 """
@@ -126,17 +128,23 @@ def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAUL
     return dict(rec, cached=False)
 
 
-def tune_frame(handle, disp, out, stream, replays: int = 5, waves=WAVES) -> dict:
-    """Pick and apply waves per column of the per-frame path for frames of
-    this size; returns the timings."""
+def tune_frame(handle, disp, out, stream, replays: int = 5, waves=WAVES,
+               placements=(1, 2)) -> dict:
+    """Pick and apply waves per column and the object prefix table placement
+    (1 HBM, 2 LDS where it fits) of the per-frame path for frames of this
+    size; returns the timings."""
     H, W = disp.shape
     timings = {}
-    for w in waves:
-        handle.set_waves(w)
-        if handle.waves(W, H) != w:
-            continue
-        timings[w] = _time(lambda: handle.compute(disp, out, stream), stream, replays)
+    for pl in placements:
+        handle.set_po_placement(pl)
+        for w in waves:
+            handle.set_waves(w)
+            if handle.waves(W, H) != w:
+                continue
+            timings[(w, pl)] = _time(lambda: handle.compute(disp, out, stream), stream, replays)
     best = min(timings, key=timings.get)
-    handle.set_waves(best)
-    return {"waves": best, "ms": timings[best],
-            "tried": {f"w{w}": round(v, 4) for w, v in sorted(timings.items())}}
+    handle.set_waves(best[0])
+    handle.set_po_placement(best[1])
+    return {"waves": best[0], "po_placement": best[1], "ms": timings[best],
+            "tried": {f"w{w}/{'lds' if pl == 2 else 'hbm'}": round(v, 4)
+                      for (w, pl), v in sorted(timings.items())}}

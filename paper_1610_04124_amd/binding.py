@@ -28,7 +28,7 @@ EXPORTS = (
     "stixels_batch_create", "stixels_batch_destroy", "stixels_batch_compute",
     "stixels_batch_capture", "stixels_batch_replay", "stixels_batch_info",
     "stixels_batch_set_workgroups", "stixels_batch_set_waves", "stixels_batch_waves",
-    "stixels_set_waves", "stixels_get_waves",
+    "stixels_set_waves", "stixels_get_waves", "stixels_set_po_placement",
     "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
     "stixels_debug_stage", "stixels_selftest_mean",
 )
@@ -120,6 +120,7 @@ def lib():
         L.stixels_batch_waves.argtypes = [vp]
         L.stixels_set_waves.argtypes = [vp, i32]
         L.stixels_get_waves.argtypes = [vp, i32, i32]
+        L.stixels_set_po_placement.argtypes = [vp, i32]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
         _lib = L
@@ -253,6 +254,12 @@ class Stixels:
         rc = lib().stixels_set_waves(self.h, int(waves))
         if rc != OK:
             self._err(rc, "stixels_set_waves")
+
+    def set_po_placement(self, placement: int) -> None:
+        """Object prefix table of the per-frame recurrence: 0 auto, 1 HBM, 2 LDS where it fits."""
+        rc = lib().stixels_set_po_placement(self.h, int(placement))
+        if rc != OK:
+            self._err(rc, "stixels_set_po_placement")
 
     def waves(self, width: int, height: int) -> int:
         """Wavefronts per column that compute uses for a frame of this size."""

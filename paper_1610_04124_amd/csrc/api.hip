@@ -216,6 +216,10 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
         hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
             hipSuccess)
         rc = fail(h, STIXELS_E_HIP, "cannot read the compute unit count");
+    if (rc == STIXELS_OK &&
+        hipDeviceGetAttribute(&h->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                              h->device) != hipSuccess)
+        rc = fail(h, STIXELS_E_HIP, "cannot read the LDS size");
     if (rc == STIXELS_OK) rc = upload(h, &h->d_sky, h->sky);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_ground, h->ground);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_object_t, h->object_t);
@@ -280,7 +284,9 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
     hipError_t e = launch_reduce(m, d_disparity, width, height, ncols, ws.q, st);
     if (e == hipSuccess) e = launch_tables(m, ws, height, ncols, vtop, st);
     const int waves = frame_waves(h->waves, height, ncols, h->num_cu);
-    if (e == hipSuccess) e = launch_dp(m, ws, height, ncols, vtop, waves, fo, st);
+    if (e == hipSuccess)
+        e = launch_dp(m, ws, height, ncols, vtop, waves, frame_po_lds(h->po_placement, height),
+                      h->lds_per_block, fo, st);
     if (e != hipSuccess)
         return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     h->last_W = width;
@@ -293,6 +299,14 @@ int stixels_set_waves(stixels_handle* h, int32_t waves) {
     if (waves != 0 && waves != 1 && waves != 2 && waves != 4)
         return fail(h, STIXELS_E_INVALID_ARG, "waves per column must be 0, 1, 2 or 4");
     h->waves = waves;
+    return STIXELS_OK;
+}
+
+int stixels_set_po_placement(stixels_handle* h, int32_t placement) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (placement < 0 || placement > 2)
+        return fail(h, STIXELS_E_INVALID_ARG, "placement must be 0 (auto), 1 (HBM) or 2 (LDS)");
+    h->po_placement = placement;
     return STIXELS_OK;
 }
 

@@ -81,10 +81,13 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
 
 // S: 64-row slots (h <= 64 S); NCH: 64-entry chunks of disparity rows
 // (d_range <= 64 NCH); W: waves per column (the workgroup is 64 W lanes, all
-// of which call this function).  On return the results are written.
-template <int S, int NCH, int W>
+// of which call this function).  POL: the recurrence gathers the object
+// prefix table from po_lds, an LDS copy of in.PO (the backtracking still
+// reads in.PO).  On return the results are written.
+template <int S, int NCH, int W, bool POL = false>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out, ColumnLds<S, W>& L) {
+                             const ColumnOut& out, ColumnLds<S, W>& L,
+                             const float* po_lds = nullptr) {
     static_assert(W == 1 || W == 2 || W == 4, "waves per column");
     constexpr int SW = (S + W - 1) / W;              // slots per wave
     const int lane = threadIdx.x & 63;
@@ -94,6 +97,17 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     const int fbase = in.fbase, fmax = in.fmax;
     const int nrow = fmax - fbase + 1;               // <= d_range <= 64 * NCH
     const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
+    // object prefix entry at byte offset `off` of the column's table; the
+    // LDS copy clamps the offset to the table (rows past the column's height
+    // form arbitrary offsets), the buffer resource reads 0 past its end
+    const uint32_t po_last = (uint32_t)nrow * stride4 - 4u;
+    auto po_at = [&](uint32_t off, uint32_t soff) -> float {
+        if constexpr (POL) {
+            return po_lds[__builtin_elementwise_min(off + soff, po_last) >> 2];
+        } else {
+            return buf_load_b(po, off, soff);
+        }
+    };
     const float eps = P.mean_eps;
     const float cmean = eps - (float)fbase;          // mean_index gives f - fbase
     const float INF = inf_f();
@@ -129,8 +143,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         eA[t] = in.PA[kk];
         eN[t] = in.PN2[kk];
         const int fi = mean_index(eA[t], eN[t], cmean);
-        mO[t] = buf_load_b(po, __umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0) +
-                P.first[0];
+        mO[t] = po_at(__umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
         fO[t] = fi;
     }
 
@@ -293,7 +306,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 const int s = t * W + wave;
                 if (s < sj) continue;
                 const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
-                pk[t] = buf_load_b(po, __umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
+                pk[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
                 qv[t] = qtab[fi & 255u];               // fi < 64 NCH except in rows past H
                 fS[t] = (int)fi;
             }

@@ -171,11 +171,41 @@ struct DpArgs {
     float* total;
     uint8_t* overflow;
     int cap, H, ncols, D, vtop;
+    int lds_floats;         // dynamic LDS of a POL launch, in floats
     Prior prior;
 };
 
-// One workgroup of W waves per column.
-template <int S, int NCH, int W>
+// n floats from global memory into LDS by the W waves of the workgroup, and
+// a barrier.  The 16-byte-aligned body goes through direct global-to-LDS
+// loads (lane l of a wave fills bytes [16 l, 16 l + 16) above the wave's
+// LDS base; no register round trip, many loads in flight); the tail, and a
+// source that is not 16-byte aligned, through ordinary loads.  Nothing past
+// g[n-1] is read.
+template <int W>
+__device__ void copy_to_lds(float* lds, const float* g, int n) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    int done = 0;
+    if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
+        const int n4 = n & ~3;
+        for (int base = wave * 256; base < n4; base += 256 * W) {
+            const int i = base + 4 * lane;
+            if (i < n4)
+                __builtin_amdgcn_global_load_lds(g + i,
+                                                 (__attribute__((address_space(3))) void*)(lds + base),
+                                                 16, 0, 0);
+        }
+        done = n4;
+    }
+    for (int i = done + (int)threadIdx.x; i < n; i += 64 * W) lds[i] = g[i];
+    __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed
+    __syncthreads();
+}
+
+// One workgroup of W waves per column.  POL: the column's object prefix
+// table is copied into dynamic LDS when it fits (one copy, contiguous rows),
+// so that the recurrence gathers from LDS instead of the caches and HBM.
+template <int S, int NCH, int W, bool POL>
 __global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
     __shared__ int16_t qs[64 * S];
     __shared__ ColumnLds<S, W> lds;
@@ -202,7 +232,16 @@ __global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
     out.total = a.total + col;
     out.overflow = a.overflow + col;
     out.cap = a.cap;
-    solve_column<S, NCH, W>(a.H, a.vtop, a.prior, in, out, lds);
+    if constexpr (POL) {
+        extern __shared__ float po_lds[];
+        const int n = (in.fmax - in.fbase + 1) * stride;   // uniform over the workgroup
+        if (n <= a.lds_floats) {
+            copy_to_lds<W>(po_lds, in.PO, n);
+            solve_column<S, NCH, W, true>(a.H, a.vtop, a.prior, in, out, lds, po_lds);
+            return;
+        }
+    }
+    solve_column<S, NCH, W, false>(a.H, a.vtop, a.prior, in, out, lds);
 }
 
 // ------------------------------------------------------------------ self-test
@@ -276,16 +315,65 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
 int frame_waves(int requested, int H, int ncols, int num_cu) {
     const int slots = kernel_slots(H);
     if (requested > 0) return std::min(requested, slots >= 4 ? 4 : (slots >= 2 ? 2 : 1));
-    // automatic: the most waves per column that keep the frame within about
-    // two waves per SIMD
+    // automatic: one wave per column (a recurrence step is bound by the
+    // latency of its gathers, which more waves do not shorten) unless the
+    // frame has fewer columns than the device has compute units
     for (int w : {4, 2}) {
-        if (w <= slots && (long long)ncols * w <= 8LL * num_cu) return w;
+        if (w <= slots && (long long)ncols * w <= (long long)num_cu) return w;
     }
     return 1;
 }
 
+namespace {
+
+// Largest POL dynamic LDS (bytes) of a variant on the current device, set
+// once per variant as the kernel's limit; 0 if the device refuses.
+template <int S, int NCH, int W>
+int pol_lds_bytes(int lds_per_block) {
+    static int bytes = -1;
+    if (bytes < 0) {
+        hipFuncAttributes fa{};
+        const void* f = reinterpret_cast<const void*>(&dp_kernel<S, NCH, W, true>);
+        int b = 0;
+        if (hipFuncGetAttributes(&fa, f) == hipSuccess) {
+            b = lds_per_block - (int)fa.sharedSizeBytes;
+            b = (b / 16) * 16;
+            if (b <= 0 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) !=
+                              hipSuccess)
+                b = 0;
+        }
+        bytes = b;
+    }
+    return bytes;
+}
+
+template <int S, int NCH, int W>
+void launch_dp_variant(const DpArgs& a0, bool pol, int lds_per_block, int ncols, hipStream_t st) {
+    DpArgs a = a0;
+    if constexpr (S <= 8) {
+        const int bytes = pol ? pol_lds_bytes<S, NCH, W>(lds_per_block) : 0;
+        if (bytes > 0) {
+            a.lds_floats = bytes / 4;
+            hipLaunchKernelGGL((dp_kernel<S, NCH, W, true>), dim3(ncols), dim3(64 * W),
+                               (size_t)bytes, st, a);
+            return;
+        }
+    }
+    a.lds_floats = 0;
+    hipLaunchKernelGGL((dp_kernel<S, NCH, W, false>), dim3(ncols), dim3(64 * W), 0, st, a);
+}
+
+}  // namespace
+
+bool frame_po_lds(int placement, int H) {
+    // automatic: LDS for columns of up to 512 rows (a table of up to about
+    // 80 disparity rows then fits)
+    return placement == 2 || (placement == 0 && kernel_slots(H) <= 8);
+}
+
 hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
-                     int waves, const FrameOutput& out, hipStream_t st) {
+                     int waves, bool po_lds, int lds_per_block, const FrameOutput& out,
+                     hipStream_t st) {
     DpArgs a;
     a.q = ws.q;
     a.object_df = m.object_df;
@@ -303,14 +391,14 @@ hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int 
     a.ncols = ncols;
     a.D = m.D;
     a.vtop = vtop;
+    a.lds_floats = 0;
     a.prior = m.prior;
     const int slots = kernel_slots(H), nch = kernel_chunks(m.D);
-    const dim3 g(ncols), b(64 * waves);
     bool launched = false;
-#define STX_CASE(n, c, w)                                               \
-    if (slots == n && nch == c && waves == w) {                         \
-        hipLaunchKernelGGL((dp_kernel<n, c, w>), g, b, 0, st, a);       \
-        launched = true;                                                \
+#define STX_CASE(n, c, w)                                                 \
+    if (slots == n && nch == c && waves == w) {                           \
+        launch_dp_variant<n, c, w>(a, po_lds, lds_per_block, ncols, st);  \
+        launched = true;                                                  \
     }
     STX_FOR_EACH_VARIANT(STX_CASE)
 #undef STX_CASE

@@ -14,6 +14,8 @@ struct stixels_handle {
     int device = 0;
     int num_cu = 0;
     int waves = 0;          // waves per column of the recurrence (0 = automatic)
+    int po_placement = 0;   // object prefix table of the recurrence: 0 auto, 1 HBM, 2 LDS
+    int lds_per_block = 0;  // bytes
     // host copies of the rounded tables
     std::vector<float> sky, ground, object_t, object_df;
     std::vector<int32_t> fg_hi, fg_lo;

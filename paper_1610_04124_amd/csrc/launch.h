@@ -47,8 +47,13 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
 // Waves per column of the per-frame recurrence: `requested` (1, 2 or 4,
 // capped by the slot count) or, for 0, an automatic choice.
 int frame_waves(int requested, int H, int ncols, int num_cu);
+// Whether the per-frame recurrence tries the LDS copy of the object prefix
+// table: placement 0 automatic, 1 never (HBM), 2 wherever it fits.
+bool frame_po_lds(int placement, int H);
+// lds_per_block: the device's LDS limit per workgroup (bytes).
 hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int ncols, int vtop,
-                     int waves, const FrameOutput& out, hipStream_t st);
+                     int waves, bool po_lds, int lds_per_block, const FrameOutput& out,
+                     hipStream_t st);
 hipError_t run_selftest_mean(int D, int max_height, int64_t* mismatches);
 
 // Bottom-up row limit of ground stixels for a frame of height H (FP64, the

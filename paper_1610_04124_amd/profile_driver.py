@@ -28,6 +28,9 @@ def main():
     ap.add_argument("--mode", choices=["batch", "hires", "frame", "copy"], default="batch")
     ap.add_argument("--launches", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--waves", type=int, default=0, help="waves per column (frame mode; 0 auto)")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="object prefix table placement (frame mode): 0 auto, 1 HBM, 2 LDS")
     args = ap.parse_args()
 
     import torch
@@ -56,6 +59,8 @@ def main():
         params = synth.make_params()
         specs = [synth.SceneSpec(seed=i) for i in range(nframes)]
     h = P.Stixels(params)
+    h.set_waves(args.waves)
+    h.set_po_placement(args.placement)
     frames = [torch.from_numpy(synth.generate_frame(sp)).to(dev) for sp in specs]
     outs = [h.new_output(W, H) for _ in frames]
     stream = torch.cuda.Stream()

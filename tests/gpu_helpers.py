@@ -29,13 +29,16 @@ def to_device(a: np.ndarray):
 
 
 def gpu_frame(handle: P.Stixels, disp: np.ndarray, capacity: int | None = None,
-              waves: int | None = None) -> dict:
+              waves: int | None = None, po_placement: int | None = None) -> dict:
     """One frame through stixels_compute; `waves` sets the wavefronts per
-    column first (and must be honoured for the frame's height)."""
+    column first (and must be honoured for the frame's height),
+    `po_placement` the object prefix table placement (1 HBM, 2 LDS)."""
     import torch
     H, W = disp.shape
     cap = capacity if capacity else handle.capacity(H)
     out = P.FrameOutput(handle.num_columns(W), cap, device())
+    if po_placement is not None:
+        handle.set_po_placement(po_placement)
     if waves is not None:
         handle.set_waves(waves)
         assert handle.waves(W, H) == waves, (waves, handle.waves(W, H))

@@ -250,6 +250,26 @@ def test_deterministic_and_reusable():
     assert np.array_equal(a["records"], b["records"])
 
 
+@pytest.mark.parametrize("W,H,s,D,waves,placement,seed", [
+    (1024, 440, 5, 128, 1, 2, 0), (1024, 440, 5, 128, 4, 2, 1), (1024, 440, 5, 128, 1, 1, 2),
+    (300, 440, 5, 256, 1, 2, 3), (300, 440, 5, 256, 2, 2, 4), (97, 129, 3, 64, 2, 2, 5),
+    (50, 512, 5, 128, 4, 2, 6), (64, 1, 1, 16, 1, 2, 7), (80, 65, 5, 256, 1, 2, 8),
+])
+def test_frame_parity_po_placement(W, H, s, D, waves, placement, seed):
+    """Object prefix table in LDS (where it fits, per column) or in HBM; the
+    random-column frames mix tables that fit with tables that do not."""
+    announce(f"po placement {placement} W={W} H={H} s={s} D={D} waves={waves} seed={seed}")
+    if W == 1024:
+        p, h = handle_for(W, H, s=s, D=D)
+        disp = synth.generate_frame(synth.SceneSpec(seed=seed))
+    else:
+        cam = dict(synth.CAMERA_1024x440, horizon_row=float(seed * 37 % H))
+        p, h = handle_for(W, H, s=s, D=D, camera=cam)
+        disp = synth.random_columns_frame(seed, W, H, D)
+    got = gpu_frame(h, disp, waves=waves, po_placement=placement)
+    assert_frames_equal(got, oracle.frame(p, disp), f"po placement {placement} {W}x{H}")
+
+
 def test_waves_setting():
     announce("waves setting")
     p, h = handle_for(1024, 440)
@@ -263,6 +283,10 @@ def test_waves_setting():
     for bad in (3, 5, -1, 8):
         with pytest.raises(B.StixelsError) as ei:
             h.set_waves(bad)
+        assert ei.value.code == B.E_INVALID_ARG
+    for bad in (-1, 3):
+        with pytest.raises(B.StixelsError) as ei:
+            h.set_po_placement(bad)
         assert ei.value.code == B.E_INVALID_ARG
 
 

@@ -164,6 +164,7 @@ def test_create_and_batch_reject_bad_arguments_without_a_device():
     assert L.stixels_destroy(None) == 0 and L.stixels_batch_destroy(None) == 0
     assert L.stixels_set_waves(None, 1) == B.E_INVALID_ARG
     assert L.stixels_get_waves(None, 440, 1024) == 0
+    assert L.stixels_set_po_placement(None, 1) == B.E_INVALID_ARG
     assert L.stixels_batch_set_waves(None, 2) == B.E_INVALID_ARG
     assert L.stixels_batch_waves(None) == 0
     assert L.stixels_selftest_mean(1, 10, None) == B.E_INVALID_ARG
