@@ -50,10 +50,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel):
+def traffic_from_profiles(kernel, workgroups):
     """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary, if it was taken on the current kernel sources and on the same
-    kernel variant."""
+    summary, if it was taken on the current kernel sources, on the same
+    kernel variant and with the same number of workgroups."""
     path = os.path.join(ROOT, "profiles", "batch_kernel_1024x440_b64_traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,7 +61,8 @@ def traffic_from_profiles(kernel):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel:
+    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel
+            or d.get("workgroups") != workgroups):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -258,7 +259,7 @@ def main():
     ops = OPS_PER_PAIR * pairs_per_frame() * FRAMES
     achieved = ops / avg_launch_s
     kernel = f"batch_kernel<7, 2, {waves}>"
-    traffic = traffic_from_profiles(kernel)
+    traffic = traffic_from_profiles(kernel, grid)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK / 1e12, 4),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
                 "kernel": kernel, "ops_per_launch": ops,

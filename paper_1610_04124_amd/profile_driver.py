@@ -28,7 +28,10 @@ def main():
     ap.add_argument("--mode", choices=["batch", "hires", "frame", "copy"], default="batch")
     ap.add_argument("--launches", type=int, default=3)
     ap.add_argument("--frames", type=int, default=64)
-    ap.add_argument("--waves", type=int, default=0, help="waves per column (frame mode; 0 auto)")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="waves per column (0: automatic per frame, one per column batched)")
+    ap.add_argument("--workgroups", type=int, default=0,
+                    help="resident workgroups of the batched launch (0: the occupancy limit)")
     ap.add_argument("--placement", type=int, default=0,
                     help="object prefix table placement (frame mode): 0 auto, 1 HBM, 2 LDS")
     args = ap.parse_args()
@@ -66,7 +69,8 @@ def main():
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
     if args.mode in ("batch", "hires"):
-        b = P.Batch(len(frames), len(frames) * (W // 5), H, D)
+        b = P.Batch(len(frames), len(frames) * (W // 5), H, D, args.workgroups)
+        b.set_waves(args.waves)
         b.capture(list(zip([h] * len(frames), frames, outs)), stream)
         for _ in range(args.launches):
             b.replay(stream)
