@@ -147,11 +147,19 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
 
         // Sec. 4.2: prefix tables into the scratch slot: the four small ones
         // by wave 0, the object rows f = fmin + wave, fmin + wave + W, ...
+        // Every load of a table row (one per 64-row slot) is issued before
+        // its scan starts, so a row costs one memory latency rather than one
+        // per slot.
         float* PG = ws;
         float* PS = ws + stride;
         float* PA = ws + 2 * stride;
         float* PN = ws + 3 * stride;
         float* PO = ws + 4 * stride;
+        const int nsl = (H + 63) >> 6;
+        auto q_at = [&](int c) {
+            const int v = 64 * c + lane;
+            return (v < H) ? (int)qs[v] : -1;
+        };
         if (wave == 0) {
             if (lane == 0) {
                 PG[0] = 0.0f;
@@ -160,9 +168,8 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
                 PN[0] = 0.0f;
             }
             float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
-            for (int base = 0; base < H; base += 64) {
-                const int v = base + lane;
-                const int x = (v < H) ? (int)qs[v] : -1;
+            for (int c = 0; c < nsl; ++c) {
+                const int v = 64 * c + lane, x = q_at(c);
                 float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
                 if (x >= 0) {
                     g = J.ground[(size_t)(H - 1 - v) * D + x];
@@ -186,16 +193,24 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
                 cn = readlane_f(nn, 63);
             }
         }
+        const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+#pragma unroll 1
         for (int f = fmin + wave; f <= fmax; f += W) {
-            const float* orow = J.object_t + (size_t)f * D;
+            float oc[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                if (c >= nsl) break;
+                const int x = q_at(c);
+                oc[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
+            }
             float* prow = PO + (size_t)(f - fmin) * stride;
             if (lane == 0) prow[0] = 0.0f;
             float carry = 0.0f;
-            for (int base = 0; base < H; base += 64) {
-                const int v = base + lane;
-                const int x = (v < H) ? (int)qs[v] : -1;
-                float o = (x >= 0) ? orow[x] : 0.0f;
-                o = wave_inclusive_scan(o) + carry;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                if (c >= nsl) break;
+                const int v = 64 * c + lane;
+                const float o = wave_inclusive_scan(oc[c]) + carry;
                 if (v < H) prow[v + 1] = o;
                 carry = readlane_f(o, 63);
             }

@@ -140,17 +140,31 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
         }
     }
 
+    // Object rows: every load of a row (one per 64-row slot) is issued
+    // before its scan starts, so a row costs one memory latency rather than
+    // one per slot.
     float* PO = a.po + (size_t)col * D * stride;
+    const int nsl = (H + 63) >> 6;
+    const auto otr = make_rsrc(a.object_t, (uint32_t)(D * D) * 4u);
+#pragma unroll 1
     for (int f = fmin + wave; f <= fmax; f += 8) {
-        const float* orow = a.object_t + (size_t)f * D;
+        constexpr int kSlots = kMaxHeight / 64;
+        float oc[kSlots];
+#pragma unroll
+        for (int c = 0; c < kSlots; ++c) {
+            if (c >= nsl) break;
+            const int v = 64 * c + lane;
+            const int x = (v < H) ? (int)qs[v] : -1;
+            oc[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
+        }
         float* prow = PO + (size_t)(f - fmin) * stride;
         if (lane == 0) prow[0] = 0.0f;
         float carry = 0.0f;
-        for (int base = 0; base < H; base += 64) {
-            const int v = base + lane;
-            const int x = (v < H) ? (int)qs[v] : -1;
-            float o = (x >= 0) ? orow[x] : 0.0f;
-            o = wave_inclusive_scan(o) + carry;
+#pragma unroll
+        for (int c = 0; c < kSlots; ++c) {
+            if (c >= nsl) break;
+            const int v = 64 * c + lane;
+            const float o = wave_inclusive_scan(oc[c]) + carry;
             if (v < H) prow[v + 1] = o;
             carry = readlane_f(o, 63);
         }
