@@ -160,7 +160,9 @@ int stixels_get_waves(const stixels_handle *h, int32_t height, int32_t width);
  * global memory (HBM and the caches); 2 = copied into the workgroup's LDS
  * when the column's table (its disparity rows x (height+1) floats) fits,
  * else global memory; 0 (the default) = as 2 for heights up to 512, as 1
- * above.  Results do not depend on it.  STIXELS_E_INVALID_ARG otherwise. */
+ * above.  The LDS copy applies to one wave per column and max_disparity
+ * <= 128; other launches read global memory.  Results do not depend on it.
+ * STIXELS_E_INVALID_ARG for other values. */
 int stixels_set_po_placement(stixels_handle *h, int32_t placement);
 
 /* Text of the last error reported on this handle ("" if none); with NULL,

@@ -406,44 +406,78 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                     lf = f0;
                 }
             }
-            for (int s = 0; s < S; ++s) {
-                if (lb >= 0 || s * 64 >= k) break;
-                const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
-                const bool inr = p < k;
-                const int bb = p + 1;
-                float data;
-                int f = 0;
-                float pen_o = 0.0f, pen_g = 0.0f;
-                const float mo = L.crow_o[p], mg = L.crow_g[p], ms = L.crow_s[p];   // p < 64 S
-                if (cls == 0) {
-                    // lanes past the row (!inr) may form out-of-range
-                    // indices: the buffer bounds checks turn them into 0
-                    f = rounded_mean(kA - buf_load(par, bb), kN - buf_load(pnr, bb), eps);
-                    data = buf_load(po, (f - fbase) * stride + kk) -
-                           buf_load(po, (f - fbase) * stride + bb);
-                    pen_o = (f > (int)L.crow_f[p] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
-                    const int r = inr ? H - 1 - bb : 0;
-                    const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
-                    pen_g = (f > thi) ? P.c_dive : ((f < tlo) ? P.c_grav : 0.0f);
-                } else if (cls == 1) {
-                    // ground stixels end at or below vtop, so PG[bb] is finite
-                    data = kG - buf_load(pgr, bb);
-                } else {
-                    data = kS - buf_load(psr, bb);
+            // The slots holding predecessor rows p < k go in groups: a group's
+            // prefix loads are issued together, then its table gathers, then
+            // its candidates are checked in b order (lanes past the row form
+            // out-of-range indices, which the buffer bounds checks read as 0).
+            constexpr int BG = (S <= 4) ? S : 4;
+            const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
+            const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
+            for (int g0 = 0; g0 < S; g0 += BG) {
+                if (lb >= 0 || g0 * 64 >= k) break;
+                float pa[BG], pn[BG], dk[BG], db[BG];
+                int fv[BG], thi[BG], tlo[BG];
+#pragma unroll
+                for (int i = 0; i < BG; ++i) {
+                    const int s = g0 + i;
+                    if (s >= S || s * 64 >= k) break;
+                    const int bb = s * 64 + lane + 1;
+                    if (cls == 0) {
+                        pa[i] = buf_load(par, bb);
+                        pn[i] = buf_load(pnr, bb);
+                    } else {
+                        pa[i] = buf_load((cls == 1) ? pgr : psr, bb);
+                    }
                 }
-                const float co = mo + tO + pen_o + data;
-                const float cg = mg + tG + pen_g + data;
-                const float cs = ms + tS + data;
-                const int code = !inr ? 3
-                               : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
-                const uint64_t m = __ballot(code < 3);
-                if (m) {
-                    const int l0 = (int)__builtin_ctzll(m);
-                    lb = s * 64 + l0 + 1;
-                    lc = readlane_i(code, l0);
-                    lf = readlane_i(f, l0);
-                    const float pc = (lc == 0) ? mo : ((lc == 1) ? mg : ms);
-                    prevC = readlane_f(pc, l0);
+                if (cls == 0) {
+#pragma unroll
+                    for (int i = 0; i < BG; ++i) {
+                        const int s = g0 + i;
+                        if (s >= S || s * 64 >= k) break;
+                        const int p = s * 64 + lane, bb = p + 1;
+                        const int f = rounded_mean(kA - pa[i], kN - pn[i], eps);
+                        fv[i] = f;
+                        dk[i] = buf_load(po, (f - fbase) * stride + kk);
+                        db[i] = buf_load(po, (f - fbase) * stride + bb);
+                        const int r = (p < k) ? H - 1 - bb : 0;
+                        thi[i] = __builtin_bit_cast(int, buf_load(fgh, r));
+                        tlo[i] = __builtin_bit_cast(int, buf_load(fgl, r));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < BG; ++i) {
+                    const int s = g0 + i;
+                    if (s >= S || s * 64 >= k) break;
+                    const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
+                    const bool inr = p < k;
+                    float data;
+                    int f = 0;
+                    float pen_o = 0.0f, pen_g = 0.0f;
+                    const float mo = L.crow_o[p], mg = L.crow_g[p], ms = L.crow_s[p];   // p < 64 S
+                    if (cls == 0) {
+                        f = fv[i];
+                        data = dk[i] - db[i];
+                        pen_o = (f > (int)L.crow_f[p] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
+                        pen_g = (f > thi[i]) ? P.c_dive : ((f < tlo[i]) ? P.c_grav : 0.0f);
+                    } else {
+                        // ground stixels end at or below vtop, so PG[p+1] is finite
+                        data = ((cls == 1) ? kG : kS) - pa[i];
+                    }
+                    const float co = mo + tO + pen_o + data;
+                    const float cg = mg + tG + pen_g + data;
+                    const float cs = ms + tS + data;
+                    const int code = !inr ? 3
+                                   : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
+                    const uint64_t m = __ballot(code < 3);
+                    if (m) {
+                        const int l0 = (int)__builtin_ctzll(m);
+                        lb = s * 64 + l0 + 1;
+                        lc = readlane_i(code, l0);
+                        lf = readlane_i(f, l0);
+                        const float pc = (lc == 0) ? mo : ((lc == 1) ? mg : ms);
+                        prevC = readlane_f(pc, l0);
+                        break;
+                    }
                 }
             }
             if (lb < 0) return -1;

@@ -364,7 +364,10 @@ int pol_lds_bytes(int lds_per_block) {
 template <int S, int NCH, int W>
 void launch_dp_variant(const DpArgs& a0, bool pol, int lds_per_block, int ncols, hipStream_t st) {
     DpArgs a = a0;
-    if constexpr (S <= 8) {
+    // the LDS copy is built for one wave per column and d_range <= 128 only:
+    // with both recurrences in one kernel the other variants run out of
+    // registers, and they were not faster with it
+    if constexpr (S <= 8 && NCH == 2 && W == 1) {
         const int bytes = pol ? pol_lds_bytes<S, NCH, W>(lds_per_block) : 0;
         if (bytes > 0) {
             a.lds_floats = bytes / 4;
