@@ -194,25 +194,47 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             }
         }
         const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
-#pragma unroll 1
-        for (int f = fmin + wave; f <= fmax; f += W) {
-            float oc[S];
+        // the column's object rows, stored through one buffer resource with a
+        // per-lane offset and the row's offset in a scalar register
+        const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+        // With several waves per column the loads of row f + W are in flight
+        // while row f is scanned; one-wave workgroups have no registers to
+        // spare for it (measured: double buffering made them spill and run
+        // slower) and load each row just before scanning it.
+        constexpr bool DB = (W > 1);
+        float oc[S], on[S];
+        auto load_row = [&](float (&o)[S], int f) {
 #pragma unroll
             for (int c = 0; c < S; ++c) {
                 if (c >= nsl) break;
                 const int x = q_at(c);
-                oc[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
+                o[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
             }
-            float* prow = PO + (size_t)(f - fmin) * stride;
-            if (lane == 0) prow[0] = 0.0f;
+        };
+        if constexpr (DB) {
+            if (fmin + wave <= fmax) load_row(oc, fmin + wave);
+        }
+#pragma unroll 1
+        for (int f = fmin + wave; f <= fmax; f += W) {
+            if constexpr (DB) {
+                if (f + W <= fmax) load_row(on, f + W);
+            } else {
+                load_row(oc, f);
+            }
+            const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
+            if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
             float carry = 0.0f;
 #pragma unroll
             for (int c = 0; c < S; ++c) {
                 if (c >= nsl) break;
                 const int v = 64 * c + lane;
                 const float o = wave_inclusive_scan(oc[c]) + carry;
-                if (v < H) prow[v + 1] = o;
+                if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
                 carry = readlane_f(o, 63);
+            }
+            if constexpr (DB) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) oc[c] = on[c];
             }
         }
         __syncthreads();   // the tables written above are read back below, by every wave

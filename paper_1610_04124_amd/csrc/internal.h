@@ -194,4 +194,13 @@ __device__ __forceinline__ float buf_load_b(__amdgpu_buffer_rsrc_t r, uint32_t v
                               __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
 
+// Store a float through a buffer resource at a per-lane byte offset plus a
+// wave-uniform byte offset (SGPR).  A vector-memory store; an offset past
+// the resource's size is dropped.
+__device__ __forceinline__ void buf_store_b(__amdgpu_buffer_rsrc_t r, float x, uint32_t voff,
+                                            uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, (int)voff, (int)soff,
+                                          0);
+}
+
 }  // namespace stx
