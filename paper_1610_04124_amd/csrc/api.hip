@@ -231,7 +231,7 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
         bool ok = hipMalloc(reinterpret_cast<void**>(&h->d_q), nc * h->Hmax * sizeof(int16_t)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_prefix), 4 * nc * H1 * sizeof(float)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_range), 2 * nc * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(reinterpret_cast<void**>(&h->d_po), nc * h->D * H1 * sizeof(float)) == hipSuccess;
+                  hipMalloc(reinterpret_cast<void**>(&h->d_po), nc * h->D * H1 * sizeof(float) + kTableGuardBytes) == hipSuccess;
         if (!ok) rc = fail(h, STIXELS_E_NOMEM, "hipMalloc of the frame workspace failed");
     }
     if (rc != STIXELS_OK) {

@@ -482,7 +482,8 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
             hipMalloc(reinterpret_cast<void**>(&b->d_jobs_g), sizeof(JobDesc) * cfg->max_jobs) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&b->d_tasks_g), sizeof(int2) * cfg->max_tasks) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&b->d_counter_g), sizeof(unsigned int)) == hipSuccess &&
-            hipMalloc(reinterpret_cast<void**>(&b->d_scratch), sizeof(float) * b->scratch_floats) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_scratch),
+                      sizeof(float) * b->scratch_floats + kTableGuardBytes) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&b->h_jobs), sizeof(JobDesc) * cfg->max_jobs, hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc(reinterpret_cast<void**>(&b->h_tasks), sizeof(int2) * cfg->max_tasks, hipHostMallocDefault) == hipSuccess &&
             hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;

@@ -160,6 +160,16 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     const auto odf = make_rsrc(in.O_df, (uint32_t)(in.D * in.D) * 4u);
     const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
     const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
+    // per-lane byte offset of disparity row fbase + 64c + lane (2^30 past
+    // the column's range); kept in registers for two chunks, recomputed per
+    // step for four, where the registers are scarcer
+    auto row_off = [&](int c) -> uint32_t {
+        const int i = 64 * c + lane;
+        return (i < nrow) ? (uint32_t)(fbase + i) * 4u : 0x40000000u;
+    };
+    uint32_t roff[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) roff[c] = row_off(c);
     auto load_next = [&](int v) {
         // for step v: object costs of pixel q_v for every disparity row, the
         // sky and ground prefixes at v+1 (ground INF above vtop) and the
@@ -169,11 +179,14 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // top-down row >= -1; an invalid pixel or a disparity row past the
         // column's range gives index -1).
         const int qv = in.q[v];
+        // byte offset of O[qv][fbase + i]: a wave-uniform part plus a
+        // per-lane part; an invalid pixel or a disparity row past the
+        // column's range adds 2^30, far past the end of the resource (in the
+        // per-lane offset, which the bounds check always covers)
+        const uint32_t qoff = (qv >= 0) ? (uint32_t)(qv * in.D) * 4u : 0x40000000u;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int i = 64 * c + lane;
-            orow[c] = buf_load(odf, (qv >= 0 && i < nrow) ? qv * in.D + fbase + i : -1);
-        }
+        for (int c = 0; c < NCH; ++c)
+            orow[c] = buf_load_b(odf, ((NCH <= 2) ? roff[c] : row_off(c)) + qoff, 0u);
         ps_n = buf_load(psr, v + 1);
         const float pg = buf_load(pgr, v + 1);
         pg_n = (v <= vtop) ? pg : INF;

@@ -25,6 +25,11 @@ constexpr int kMaxHeight = kWave * kMaxSlots;
 constexpr int kMaxStixelWidth = 16;
 constexpr int kMaxDisparity = 256;
 constexpr uint32_t kBufferWord3 = 0x00020000u;  // raw buffer resource, gfx9 family
+// Bytes allocated past the end of every object prefix table workspace: the
+// recurrence's gathers for rows past a column's height may read up to 64 S
+// floats beyond the column's last table row (their values are never used),
+// and this keeps those reads inside the allocation.
+constexpr size_t kTableGuardBytes = 64 * 1024;
 
 // Instantiated slot counts of the recurrence kernels (64-row slots per lane);
 // a column runs on the smallest one that covers its height.
