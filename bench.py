@@ -135,6 +135,43 @@ def hires(warmup, steps, tune_launch=True):
     return out
 
 
+def mean_mode(warmup, steps, tune_launch=True):
+    """The batched headline workload with the paper's own reduction (the
+    mean of each strip's valid pixels, Sec. 4.1) instead of the median."""
+    import torch
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    dev = torch.device("cuda", 0)
+    params = synth.make_params(reduce_mode=1)
+    h = P.Stixels(params)
+    frames = [torch.from_numpy(synth.generate_frame(synth.SceneSpec(seed=i))).to(dev)
+              for i in range(FRAMES)]
+    outs = [h.new_output(W, H) for _ in frames]
+    stream = torch.cuda.Stream()
+    b = P.Batch(FRAMES, FRAMES * (W // S_WIDTH), H, D_RANGE)
+    items = list(zip([h] * FRAMES, frames, outs))
+    torch.cuda.synchronize()
+    if tune_launch:
+        from paper_1610_04124_amd.autotune import tune
+        tune(b, items, stream, cache_path=None)
+    else:
+        b.capture(items, stream)
+    for _ in range(warmup):
+        b.replay(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.replay(stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g, _ = b.info()
+    return {"fps": round(FRAMES / dt, 2), "ms_per_batch": round(dt * 1e3, 4),
+            "waves_per_column": b.waves(), "workgroups": g,
+            "reduction": "mean of the strip's valid pixels (reduce_mode 1)"}
+
+
 def serve(seconds, rate_scale=1.0):
     """8 cameras (1024x440, 1280x720, 2048x880 by camera index, stixel width
     5) at 30 Hz Poisson each (times rate_scale), served with continuous
@@ -155,6 +192,7 @@ def serve(seconds, rate_scale=1.0):
             spec = synth.SceneSpec(W, Hc, D, synth.camera_for_size(W, Hc), seed=1000 * c + i)
             frames[(c, i)] = torch.from_numpy(synth.generate_frame(spec)).to(dev)
     ex = GpuExecutor(cams, streams=3, max_frames=64)
+    waves = ex.tune({c: [frames[(c, i)] for i in range(per_cam)] for c in range(len(cams))})
     srv = Server(cams, ex, hbm_budget=8 << 30, max_batch=64, keep_outputs=False)
     arrivals = poisson_arrivals([30.0 * rate_scale] * 8, seconds, [42 + c for c in range(8)],
                                 per_cam)
@@ -164,6 +202,7 @@ def serve(seconds, rate_scale=1.0):
     st = srv.stats()
     st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
     st.update({"cameras": 8, "rate_hz_per_camera": 30 * rate_scale, "seconds": seconds,
+               "waves_per_column_by_slots": {str(k): v for k, v in sorted(waves.items())},
                "sizes": "1024x440, 1280x720, 2048x880 by camera index; stixel width 5"})
     return st
 
@@ -291,6 +330,8 @@ def main():
     if frame_tuned is not None:
         result["per_frame"]["autotune_tried_ms"] = frame_tuned["tried"]
     result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5), not args.no_tune)
+    result["batched_mean_reduction"] = mean_mode(args.warmup, max(3, args.steps // 5),
+                                                  not args.no_tune)
     if args.serve_seconds > 0:
         result["serving"] = serve(args.serve_seconds)
         # the same cameras at 16x the rate: continuous batching under load

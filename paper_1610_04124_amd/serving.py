@@ -74,6 +74,33 @@ class GpuExecutor:
         self.free = list(range(streams))
         self._torch = torch
         self._P = P
+        # waves per column of each height class (64-row slots); classes not
+        # tuned use one wave for up to 8 slots and two above, which is what
+        # the autotuner picks at 440 and 880 rows on MI355X
+        self.waves = {}
+
+    def waves_for(self, slots: int) -> int:
+        return self.waves.get(slots, 1 if slots <= 8 else 2)
+
+    def tune(self, frames_by_camera, max_frames: int = 16):
+        """Time waves per column for every height class on sample frames
+        (camera index -> list of device frames) and keep the fastest."""
+        from paper_1610_04124_amd.autotune import tune
+
+        st = self.streams[0]
+        classes = {}
+        for ci, frames in frames_by_camera.items():
+            c = self.cameras[ci]
+            for f in frames:
+                classes.setdefault((c.height + 63) // 64, []).append((c, f))
+        for slots, members in classes.items():
+            members = members[:max_frames]
+            items = [(c.handle, f, c.handle.new_output(c.width, c.height)) for c, f in members]
+            rec = tune(self.batches[0], items, st, replays=3, cache_path=None)
+            self.waves[slots] = rec["waves"]
+        self.batches[0].set_workgroups(0)
+        self._torch.cuda.synchronize()
+        return dict(self.waves)
 
     def slots(self) -> int:
         return len(self.free)
@@ -96,6 +123,7 @@ class GpuExecutor:
             groups.setdefault((self.cameras[r.camera].height + 63) // 64, []).append(r)
         for slots in sorted(groups, reverse=True):
             items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in groups[slots]]
+            self.batches[i].set_waves(self.waves_for(slots))
             self.batches[i].compute(items, st)
         ev = self._torch.cuda.Event()
         ev.record(st)

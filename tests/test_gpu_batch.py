@@ -63,6 +63,21 @@ def test_batch_waves_match_per_frame(waves):
     assert_frames_equal(outs[3].to_host(), oracle.frame(p, frames[3]), "oracle frame 3")
 
 
+def test_batch_mean_reduction_matches_oracle():
+    """The paper's mean reduction (reduce_mode 1) through the batched launch
+    at the headline size."""
+    announce("batch 8 x 1024x440 mean reduction")
+    p = synth.make_params(reduce_mode=1)
+    h = P.Stixels(p)
+    frames = [synth.generate_frame(synth.SceneSpec(seed=s)) for s in range(40, 48)]
+    outs = [h.new_output(1024, 440) for _ in frames]
+    run_batch([(h, to_device(f), o) for f, o in zip(frames, outs)])
+    for i in (0, 5):
+        assert_frames_equal(outs[i].to_host(), oracle.frame(p, frames[i]), f"mean frame {i}")
+    for i, f in enumerate(frames):
+        assert_frames_equal(outs[i].to_host(), gpu_frame(h, f), f"mean batch vs per-frame {i}")
+
+
 def uneven_items(n):
     """Frames of the uneven workload: four sizes, stixel widths 3/5/7, their
     own cameras and disparity ranges, one handle per frame."""
