@@ -143,6 +143,10 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             fmin = 0;
             fmax = 0;
         }
+        // the same in every lane; reading them from the first lane lets the
+        // compiler keep them (and the row offsets derived from them) scalar
+        fmin = __builtin_amdgcn_readfirstlane(fmin);
+        fmax = __builtin_amdgcn_readfirstlane(fmax);
         __syncthreads();
 
         // Sec. 4.2: prefix tables into the scratch slot: the four small ones
@@ -197,6 +201,16 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         // the column's object rows, stored through one buffer resource with a
         // per-lane offset and the row's offset in a scalar register
         const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+        // Byte offset of each slot's pixel within an object-cost row (2^30
+        // for an invalid pixel or a row past H: in the per-lane offset, which
+        // the bounds check always covers, so such lanes read 0); a row's
+        // offset is then the scalar part of every load.
+        uint32_t qoff[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int x = q_at(c);
+            qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+        }
         // With several waves per column the loads of row f + W are in flight
         // while row f is scanned; one-wave workgroups have no registers to
         // spare for it (measured: double buffering made them spill and run
@@ -204,12 +218,9 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         constexpr bool DB = (W > 1);
         float oc[S], on[S];
         auto load_row = [&](float (&o)[S], int f) {
+            const uint32_t rowb = (uint32_t)(f * D) * 4u;
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-                if (c >= nsl) break;
-                const int x = q_at(c);
-                o[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
-            }
+            for (int c = 0; c < S; ++c) o[c] = buf_load_b(otr, qoff[c], rowb);
         };
         if constexpr (DB) {
             if (fmin + wave <= fmax) load_row(oc, fmin + wave);
@@ -223,10 +234,11 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             }
             const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
             if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
+            // slots past H load zeros and store nothing: no per-slot branch,
+            // so the slots' scans can interleave
             float carry = 0.0f;
 #pragma unroll
             for (int c = 0; c < S; ++c) {
-                if (c >= nsl) break;
                 const int v = 64 * c + lane;
                 const float o = wave_inclusive_scan(oc[c]) + carry;
                 if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);

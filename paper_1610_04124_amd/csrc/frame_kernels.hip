@@ -142,30 +142,42 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
 
     // Object rows: every load of a row (one per 64-row slot) is issued
     // before its scan starts, so a row costs one memory latency rather than
-    // one per slot.
+    // one per slot.  Each slot's pixel becomes a byte offset within an
+    // object-cost row once (2^30 for an invalid pixel or a row past H: in the
+    // per-lane offset, which the bounds check always covers, so such lanes
+    // read 0); a row's offset is the scalar part of every load, and the
+    // slots' scans carry no branch between them.
     float* PO = a.po + (size_t)col * D * stride;
-    const int nsl = (H + 63) >> 6;
     const auto otr = make_rsrc(a.object_t, (uint32_t)(D * D) * 4u);
+    const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+    constexpr int kSlots = kMaxHeight / 64;
+    const int nsl = (H + 63) >> 6;
+    uint32_t qoff[kSlots];
+#pragma unroll
+    for (int c = 0; c < kSlots; ++c) {
+        const int v = 64 * c + lane;
+        const int x = (v < H) ? (int)qs[v] : -1;
+        qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+    }
+    const int f0 = __builtin_amdgcn_readfirstlane(fmin), f1 = __builtin_amdgcn_readfirstlane(fmax);
 #pragma unroll 1
-    for (int f = fmin + wave; f <= fmax; f += 8) {
-        constexpr int kSlots = kMaxHeight / 64;
+    for (int f = f0 + wave; f <= f1; f += 8) {
+        const uint32_t rowb = (uint32_t)(f * D) * 4u;
         float oc[kSlots];
 #pragma unroll
         for (int c = 0; c < kSlots; ++c) {
             if (c >= nsl) break;
-            const int v = 64 * c + lane;
-            const int x = (v < H) ? (int)qs[v] : -1;
-            oc[c] = buf_load(otr, (x >= 0) ? f * D + x : -1);   // -1 reads 0
+            oc[c] = buf_load_b(otr, qoff[c], rowb);
         }
-        float* prow = PO + (size_t)(f - fmin) * stride;
-        if (lane == 0) prow[0] = 0.0f;
+        const uint32_t rowoff = (uint32_t)(f - f0) * (uint32_t)stride * 4u;
+        if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
         float carry = 0.0f;
 #pragma unroll
         for (int c = 0; c < kSlots; ++c) {
             if (c >= nsl) break;
             const int v = 64 * c + lane;
             const float o = wave_inclusive_scan(oc[c]) + carry;
-            if (v < H) prow[v + 1] = o;
+            if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
             carry = readlane_f(o, 63);
         }
     }
