@@ -250,6 +250,7 @@ def main():
         tuned = tune(batch, items, stream, cache_path=None)
     grid, ntasks = batch.info()
     waves = batch.waves()
+    columns = batch.columns()
     for _ in range(args.warmup):
         batch.replay(stream)
     torch.cuda.synchronize()
@@ -297,7 +298,7 @@ def main():
     # ---------------- roofline of the persistent kernel
     ops = OPS_PER_PAIR * pairs_per_frame() * FRAMES
     achieved = ops / avg_launch_s
-    kernel = f"batch_kernel<7, 2, {waves}>"
+    kernel = f"batch_kernel<7, 2, {waves}>" if columns == 1 else "batch_pair_kernel<7, 2>"
     traffic = traffic_from_profiles(kernel, grid)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK / 1e12, 4),
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
@@ -313,7 +314,8 @@ def main():
                    "height": H, "stixel_width": S_WIDTH, "max_disparity": D_RANGE,
                    "columns_per_frame": W // S_WIDTH,
                    "path": "persistent batched launch replayed from a HIP graph",
-                   "workgroups": grid, "tasks": ntasks, "waves_per_column": waves},
+                   "workgroups": grid, "tasks": ntasks, "waves_per_column": waves,
+                   "columns_per_wave": columns},
         "batched": {"fps": round(batched_fps, 2),
                     "batch_latency_ms_p50": round(percentile(launch_ms, 0.5), 4),
                     "batch_latency_ms_p99": round(percentile(launch_ms, 0.99), 4)},

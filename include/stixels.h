@@ -229,6 +229,16 @@ int stixels_batch_set_waves(stixels_batch *b, int32_t waves);
 /* Waves per column of the last compute or capture (0 before the first). */
 int stixels_batch_waves(const stixels_batch *b);
 
+/* Columns per wave64 of later calls: 1, or 2 (two columns of one frame
+ * share a wave, one per 32-lane half, so that the recurrence's per-step work
+ * serves both), which applies where h <= 512 and d_range <= 128 and with
+ * one wave per column; 0 = 1.  Results do not depend on it.  Used by the
+ * autotuner; takes effect at the next compute or capture. */
+int stixels_batch_set_columns(stixels_batch *b, int32_t columns);
+
+/* Columns per wave of the last compute or capture (0 before the first). */
+int stixels_batch_columns(const stixels_batch *b);
+
 /* Workgroups of the persistent launch last used, and the number of
  * tasks (frame columns) of the last call. */
 int stixels_batch_info(const stixels_batch *b, int32_t *workgroups, int32_t *tasks);

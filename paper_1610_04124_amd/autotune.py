@@ -1,9 +1,11 @@
 """Autotuner of the batched launch and of the per-frame path.
 
-Batched launch: two tunables.  Waves per column (1, 2 or 4 wave64s share a
+Batched launch: three tunables.  Waves per column (1, 2 or 4 wave64s share a
 column's rows): more waves shorten each column and, with fewer columns in
 flight, shrink the set of object prefix tables the caches have to hold, at
-the price of one barrier per recurrence step.  Resident workgroups of the
+the price of one barrier per recurrence step.  Columns per wave (1, or 2
+with one column per 32-lane half, which shares the per-step work between two
+columns at the price of more registers).  Resident workgroups of the
 persistent kernel: more hide more latency; fewer leave each SIMD less
 contended and shorten the tail when the column tasks do not divide evenly
 into the resident set.  For a job list the tuner captures the launch once
@@ -96,35 +98,44 @@ def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAUL
     with the chosen configuration."""
     key = device_key() + "||" + signature(items)
     cache = _load(cache_path) if cache_path else {}
-    if not force and key in cache and "waves" in cache[key]:
+    if not force and key in cache and "columns" in cache[key]:
         rec = cache[key]
+        batch.set_columns(rec["columns"])
         batch.set_waves(rec["waves"])
         batch.set_workgroups(rec["workgroups"])
         batch.capture(items, stream)
         return dict(rec, cached=True)
 
+    # layouts: (waves per column, columns per wave); two columns per wave
+    # only pair with one wave per column
+    layouts = [(w, 1) for w in waves] + ([(1, 2)] if 1 in waves else [])
     timings = {}
-    ntasks = 0
-    for w in waves:
+    ntasks = {}
+    for w, c in layouts:
         batch.set_waves(w)
+        batch.set_columns(c)
         batch.set_workgroups(0)
         batch.capture(items, stream)
-        if batch.waves() != w:
-            continue                               # capped by the row slots
-        gmax, ntasks = batch.info()
-        for g in candidates(gmax, ntasks):
+        if batch.waves() != w or batch.columns() != c:
+            continue                               # not available for these rows
+        gmax, nt = batch.info()
+        for g in candidates(gmax, nt):
             batch.set_workgroups(g)
             batch.capture(items, stream)
-            timings[(w, g)] = _time(lambda: batch.replay(stream), stream, replays)
-    # near-ties (within 1 %) go to fewer waves per column, then fewer
-    # workgroups: the same speed for less of the device
+            timings[(c, w, g)] = _time(lambda: batch.replay(stream), stream, replays)
+            ntasks[(c, w, g)] = nt
+    # near-ties (within 1 %) go to one column per wave, fewer waves per
+    # column, then fewer workgroups: the same speed for less of the device
     fastest = min(timings.values())
-    best = min((k for k, v in timings.items() if v <= fastest * 1.01), key=lambda k: (k[0], k[1]))
-    batch.set_waves(best[0])
-    batch.set_workgroups(best[1])
+    best = min((k for k, v in timings.items() if v <= fastest * 1.01), key=lambda k: k)
+    batch.set_columns(best[0])
+    batch.set_waves(best[1])
+    batch.set_workgroups(best[2])
     batch.capture(items, stream)
-    rec = {"waves": best[0], "workgroups": best[1], "ms": timings[best], "tasks": ntasks,
-           "tried": {f"w{w}/g{g}": round(v, 4) for (w, g), v in sorted(timings.items())}}
+    rec = {"columns": best[0], "waves": best[1], "workgroups": best[2], "ms": timings[best],
+           "tasks": ntasks[best],
+           "tried": {(f"c{c}/" if c > 1 else "") + f"w{w}/g{g}": round(v, 4)
+                     for (c, w, g), v in sorted(timings.items())}}
     if cache_path:
         cache[key] = rec
         _store(cache_path, cache)

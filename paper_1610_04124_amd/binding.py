@@ -28,6 +28,7 @@ EXPORTS = (
     "stixels_batch_create", "stixels_batch_destroy", "stixels_batch_compute",
     "stixels_batch_capture", "stixels_batch_replay", "stixels_batch_info",
     "stixels_batch_set_workgroups", "stixels_batch_set_waves", "stixels_batch_waves",
+    "stixels_batch_set_columns", "stixels_batch_columns",
     "stixels_set_waves", "stixels_get_waves", "stixels_set_po_placement",
     "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
     "stixels_debug_stage", "stixels_selftest_mean",
@@ -118,6 +119,8 @@ def lib():
         L.stixels_batch_set_workgroups.argtypes = [vp, i32]
         L.stixels_batch_set_waves.argtypes = [vp, i32]
         L.stixels_batch_waves.argtypes = [vp]
+        L.stixels_batch_set_columns.argtypes = [vp, i32]
+        L.stixels_batch_columns.argtypes = [vp]
         L.stixels_set_waves.argtypes = [vp, i32]
         L.stixels_get_waves.argtypes = [vp, i32, i32]
         L.stixels_set_po_placement.argtypes = [vp, i32]
@@ -422,6 +425,16 @@ class Batch:
     def waves(self) -> int:
         """Wavefronts per column of the last launch."""
         return int(lib().stixels_batch_waves(self.b))
+
+    def set_columns(self, columns: int):
+        """Columns per wave64 of later launches (1, 2; 0 = 1)."""
+        rc = lib().stixels_batch_set_columns(self.b, int(columns))
+        if rc != OK:
+            self._err(rc, "stixels_batch_set_columns")
+
+    def columns(self) -> int:
+        """Columns per wave of the last launch."""
+        return int(lib().stixels_batch_columns(self.b))
 
     def set_workgroups(self, n: int):
         rc = lib().stixels_batch_set_workgroups(self.b, int(n))

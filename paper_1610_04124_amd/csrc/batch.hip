@@ -276,6 +276,194 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     }
 }
 
+// Sec. 4.1-4.2 for one column by one wave: its strips reduced into qs (LDS,
+// bottom-up; -1 past H and for a column that does not exist), then its
+// prefix tables at ws (PG, PS, PA, PN at 0..3 (h+1), the object rows from
+// po_at floats on).  Returns the column's disparity range [fmin, fmax].
+template <int S>
+__device__ void column_tables(const JobDesc& J, const int col, const bool exists, int16_t* qs,
+                              float* ws, const int po_at, int& fmin_out, int& fmax_out) {
+    const int lane = threadIdx.x & 63;
+    const int H = J.H, D = J.D, stride = H + 1;
+    int lmin = INT_MAX, lmax = -1;
+    bool inv = false;
+    for (int v = lane; v < 64 * S; v += 64) {
+        int x = -1;
+        if (exists && v < H)
+            x = reduce_any(J.disp + (size_t)(H - 1 - v) * J.W + (size_t)col * J.s, J.s,
+                           J.reduce_mode, D);
+        qs[v] = (int16_t)x;
+        if (x >= 0) {
+            lmin = min(lmin, x);
+            lmax = max(lmax, x);
+        } else if (v < H) {
+            inv = true;
+        }
+    }
+    int fmin = __ballot(inv) ? 0 : wave_min_i(lmin);
+    int fmax = wave_max_i(lmax);
+    if (fmax < 0) {
+        fmin = 0;
+        fmax = 0;
+    }
+    fmin = __builtin_amdgcn_readfirstlane(fmin);
+    fmax = __builtin_amdgcn_readfirstlane(fmax);
+    fmin_out = fmin;
+    fmax_out = fmax;
+    __syncthreads();
+    float* PG = ws;
+    float* PS = ws + stride;
+    float* PA = ws + 2 * stride;
+    float* PN = ws + 3 * stride;
+    if (lane == 0) {
+        PG[0] = 0.0f;
+        PS[0] = 0.0f;
+        PA[0] = 0.0f;
+        PN[0] = 0.0f;
+    }
+    float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+    for (int base = 0; base < H; base += 64) {
+        const int v = base + lane;
+        const int x = (v < H) ? (int)qs[v] : -1;
+        float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+        if (x >= 0) {
+            g = J.ground[(size_t)(H - 1 - v) * D + x];
+            sk = J.sky[x];
+            aa = (float)(2 * x + 1);
+            nn = 2.0f;
+        }
+        g = wave_inclusive_scan(g) + cg;
+        sk = wave_inclusive_scan(sk) + cs;
+        aa = wave_inclusive_scan(aa) + ca;
+        nn = wave_inclusive_scan(nn) + cn;
+        if (v < H) {
+            PG[v + 1] = g;
+            PS[v + 1] = sk;
+            PA[v + 1] = aa;
+            PN[v + 1] = nn;
+        }
+        cg = readlane_f(g, 63);
+        cs = readlane_f(sk, 63);
+        ca = readlane_f(aa, 63);
+        cn = readlane_f(nn, 63);
+    }
+    const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+    const auto pow_ =
+        make_rsrc(ws + po_at, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+    uint32_t qoff[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        const int v = 64 * c + lane;
+        const int x = (v < H) ? (int)qs[v] : -1;
+        qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+    }
+#pragma unroll 1
+    for (int f = fmin; f <= fmax; ++f) {
+        const uint32_t rowb = (uint32_t)(f * D) * 4u;
+        float oc[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) oc[c] = buf_load_b(otr, qoff[c], rowb);
+        const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
+        if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
+        float carry = 0.0f;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int v = 64 * c + lane;
+            const float o = wave_inclusive_scan(oc[c]) + carry;
+            if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
+            carry = readlane_f(o, 63);
+        }
+    }
+}
+
+// Two columns of one frame per one-wave workgroup (solve_pair): tasks are
+// (frame, even column) pairs.  The workgroup's scratch slot holds the two
+// columns' tables one column stride ((8 + D)(h+1) floats) apart.
+template <int S, int NCH>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(3))) void batch_pair_kernel(
+    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
+    unsigned int* counter, float* scratch, long long scratch_stride, int hmax) {
+    __shared__ int16_t qs2[2 * 64 * S];
+    __shared__ float qtab2[2 * 256];
+    __shared__ ColumnLds<S, 1> lds;
+    const int lane = threadIdx.x;
+    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+    (void)hmax;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = (int)atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        const JobDesc& J = jobs[tk.x];
+        const int H = J.H, D = J.D, col0 = tk.y, stride = H + 1;
+        const bool has1 = col0 + 1 < J.ncols;
+        const long long colstride = (long long)(8 + D) * stride;
+        int fmin0, fmax0, fmin1, fmax1;
+        column_tables<S>(J, col0, true, qs2, ws, 8 * stride, fmin0, fmax0);
+        column_tables<S>(J, col0 + 1, has1, qs2 + 64 * S, ws + colstride, 8 * stride, fmin1,
+                         fmax1);
+        __syncthreads();   // the tables written above are read back below
+
+        ColumnIn in0, in1;
+        for (int x = 0; x < 2; ++x) {
+            ColumnIn& in = x ? in1 : in0;
+            float* base = ws + x * colstride;
+            in.PG = base;
+            in.PS = base + stride;
+            in.PA = base + 2 * stride;
+            in.PN2 = base + 3 * stride;
+            in.rowc = base + 4 * stride;
+            in.PO = base + 8 * stride;
+            in.fbase = x ? fmin1 : fmin0;
+            in.fmax = x ? fmax1 : fmax0;
+            in.q = qs2 + x * 64 * S;
+            in.O_df = J.object_df;
+            in.D = D;
+            in.fg_hi = J.fg_hi;
+            in.fg_lo = J.fg_lo;
+        }
+        ColumnOut out0, out1;
+        for (int x = 0; x < 2; ++x) {
+            ColumnOut& out = x ? out1 : out0;
+            const int col = col0 + x;
+            out.count = J.counts + col;
+            out.rec = J.records + (size_t)col * J.cap * 3;
+            out.total = J.total + col;
+            out.overflow = J.overflow + col;
+            out.cap = J.cap;
+        }
+        solve_pair<S, NCH>(H, J.vtop, J.prior, in0, in1, out0, out1, has1, qs2, qtab2, lds);
+        __syncthreads();   // every read of the slot completes before the next task rewrites it
+    }
+}
+
+void* batch_pair_kernel_for(int slots, int nch) {
+#define STX_CASE(n, c) \
+    if (slots == n && nch == c) return reinterpret_cast<void*>(&batch_pair_kernel<n, c>);
+    STX_FOR_EACH_PAIR_VARIANT(STX_CASE)
+#undef STX_CASE
+    return nullptr;
+}
+
+hipError_t launch_pair_batch(int slots, int nch, int grid, hipStream_t st, const JobDesc* jobs,
+                             const int2* tasks, int ntasks, unsigned int* counter, float* scratch,
+                             long long stride, int hmax) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
+    bool launched = false;
+#define STX_CASE(n, c)                                                                       \
+    if (slots == n && nch == c) {                                                            \
+        hipLaunchKernelGGL((batch_pair_kernel<n, c>), dim3(grid), dim3(64), 0, st, jobs, tasks, \
+                           ntasks, counter, scratch, stride, hmax);                          \
+        launched = true;                                                                     \
+    }
+    STX_FOR_EACH_PAIR_VARIANT(STX_CASE)
+#undef STX_CASE
+    if (!launched) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 void* batch_kernel_for(int slots, int nch, int waves) {
 #define STX_CASE(n, c, w) \
     if (slots == n && nch == c && waves == w) return reinterpret_cast<void*>(&batch_kernel<n, c, w>);
@@ -324,6 +512,8 @@ struct stixels_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int waves = 1;          // requested waves per column
+    int columns = 1;        // requested columns per wave (2: the pair kernel where it exists)
+    int last_columns = 0;
     int last_grid = 0, last_tasks = 0, last_waves = 0;
     std::string err;
 };
@@ -355,7 +545,7 @@ int occupancy_grid(stixels_batch* b, int slots, int nch, int waves, int* grid) {
 // Validate the jobs and fill the pinned staging buffers: descriptors and the
 // task list in decreasing-height order.
 int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int* nch,
-          int* ntasks, long long* stride, int* hmax_out) {
+          int* ntasks, long long* stride, int* hmax_out, bool want_pairs, bool* pairs_out) {
     if (!jobs || n < 1 || n > b->cfg.max_jobs)
         return bfail(b, STIXELS_E_INVALID_ARG, "job count outside [1, max_jobs]");
     int hmax = 0, dmax = 0;
@@ -412,23 +602,37 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
         d.cap = j.out.capacity;
         d.prior = h->prior;
     }
+    // two columns per wave only where that kernel exists (h <= 512,
+    // d_range <= 128); a task is then a (frame, even column) pair
+    const bool pairs = want_pairs && kernel_slots(hmax) <= 8 && kernel_chunks(dmax) == 2;
     for (int oi = 0; oi < n; ++oi) {
         const int i = order[oi];
         const int nc = b->h_jobs[i].ncols;
-        for (int c = 0; c < nc; ++c) b->h_tasks[t++] = make_int2(i, c);
+        for (int c = 0; c < nc; c += pairs ? 2 : 1) b->h_tasks[t++] = make_int2(i, c);
     }
     *slots = kernel_slots(hmax);
     *nch = kernel_chunks(dmax);
     *ntasks = t;
-    *stride = (long long)(4 + dmax) * (hmax + 1);
+    *stride = pairs ? 2LL * (8 + dmax) * (hmax + 1) : (long long)(4 + dmax) * (hmax + 1);
+    *pairs_out = pairs;
     *hmax_out = hmax;
     return STIXELS_OK;
 }
 
-int choose_grid(stixels_batch* b, int slots, int nch, int waves, long long stride, int ntasks,
-                int* grid) {
+int pair_occupancy_grid(stixels_batch* b, int slots, int nch, int* grid) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pair_kernel_for(slots, nch), 64,
+                                                     0) != hipSuccess ||
+        per_cu < 1)
+        return bfail(b, STIXELS_E_HIP, "occupancy query failed");
+    *grid = per_cu * b->num_cu;
+    return STIXELS_OK;
+}
+
+int choose_grid(stixels_batch* b, int slots, int nch, int waves, bool pairs, long long stride,
+                int ntasks, int* grid) {
     int g = 0;
-    int rc = occupancy_grid(b, slots, nch, waves, &g);
+    int rc = pairs ? pair_occupancy_grid(b, slots, nch, &g) : occupancy_grid(b, slots, nch, waves, &g);
     if (rc != STIXELS_OK) return rc;
     if (b->cfg.workgroups > 0) g = std::min(g, (int)b->cfg.workgroups);
     const long long by_scratch = (long long)(b->scratch_floats / (size_t)stride);
@@ -487,6 +691,14 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
     if (rc == STIXELS_OK) {
         b->scratch_floats = (size_t)grid * (size_t)(4 + cfg->max_disparity) *
                             (size_t)(cfg->max_height + 1);
+        // the two-column kernel, where it exists, needs two (8 + D)(h+1)
+        // column slots per resident workgroup
+        int pgrid = 0;
+        if (slots <= 8 && kernel_chunks(cfg->max_disparity) == 2 &&
+            pair_occupancy_grid(b, slots, 2, &pgrid) == STIXELS_OK)
+            b->scratch_floats = std::max(b->scratch_floats,
+                                         (size_t)pgrid * 2 * (size_t)(8 + cfg->max_disparity) *
+                                             (size_t)(cfg->max_height + 1));
         const bool ok =
             hipMalloc(reinterpret_cast<void**>(&b->d_jobs), sizeof(JobDesc) * cfg->max_jobs) == hipSuccess &&
             hipMalloc(reinterpret_cast<void**>(&b->d_tasks), sizeof(int2) * cfg->max_tasks) == hipSuccess &&
@@ -531,20 +743,25 @@ int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (!b) return STIXELS_E_INVALID_ARG;
     int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
-    const int waves = batch_waves_for(b, slots);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, stride, ntasks, &grid);
+    bool pairs = false;
+    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax, b->columns == 2, &pairs);
+    const int waves = pairs ? 1 : batch_waves_for(b, slots);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, pairs, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
-    const hipError_t e = launch_batch(slots, nch, waves, grid, st, b->d_jobs, b->d_tasks, ntasks,
-                                      b->d_counter, b->d_scratch, stride, hmax);
+    const hipError_t e =
+        pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
+                                  b->d_counter, b->d_scratch, stride, hmax)
+              : launch_batch(slots, nch, waves, grid, st, b->d_jobs, b->d_tasks, ntasks,
+                             b->d_counter, b->d_scratch, stride, hmax);
     if (e != hipSuccess)
         return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
     b->last_grid = grid;
     b->last_tasks = ntasks;
     b->last_waves = waves;
+    b->last_columns = pairs ? 2 : 1;
     return STIXELS_OK;
 }
 
@@ -554,9 +771,10 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
         return bfail(b, STIXELS_E_INVALID_ARG, "the null stream cannot be captured; pass a created stream");
     int slots = 0, nch = 0, ntasks = 0, grid = 0, hmax = 0;
     long long stride = 0;
-    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax);
-    const int waves = batch_waves_for(b, slots);
-    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, stride, ntasks, &grid);
+    bool pairs = false;
+    int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax, b->columns == 2, &pairs);
+    const int waves = pairs ? 1 : batch_waves_for(b, slots);
+    if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, pairs, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     // the graph reads its own descriptor copy, uploaded once here
@@ -568,8 +786,11 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     destroy_graph(b);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
-    const hipError_t e = launch_batch(slots, nch, waves, grid, st, b->d_jobs_g, b->d_tasks_g,
-                                      ntasks, b->d_counter_g, b->d_scratch, stride, hmax);
+    const hipError_t e =
+        pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+                                  b->d_counter_g, b->d_scratch, stride, hmax)
+              : launch_batch(slots, nch, waves, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+                             b->d_counter_g, b->d_scratch, stride, hmax);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(st, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -584,6 +805,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     b->last_grid = grid;
     b->last_tasks = ntasks;
     b->last_waves = waves;
+    b->last_columns = pairs ? 2 : 1;
     return STIXELS_OK;
 }
 
@@ -609,6 +831,15 @@ int stixels_batch_set_waves(stixels_batch* b, int32_t waves) {
 }
 
 int stixels_batch_waves(const stixels_batch* b) { return b ? b->last_waves : 0; }
+
+int stixels_batch_set_columns(stixels_batch* b, int32_t columns) {
+    if (!b || columns < 0 || columns > 2)
+        return bfail(b, STIXELS_E_INVALID_ARG, "columns per wave must be 0, 1 or 2");
+    b->columns = columns == 0 ? 1 : columns;
+    return STIXELS_OK;
+}
+
+int stixels_batch_columns(const stixels_batch* b) { return b ? b->last_columns : 0; }
 
 int stixels_batch_info(const stixels_batch* b, int32_t* workgroups, int32_t* tasks) {
     if (!b) return STIXELS_E_INVALID_ARG;

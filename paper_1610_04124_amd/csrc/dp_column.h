@@ -40,6 +40,8 @@ struct ColumnIn {
     int D;
     const int32_t* fg_hi;   // diving threshold per top-down image row
     const int32_t* fg_lo;   // gravity threshold per top-down image row
+    float* rowc;            // [4][H+1] final object, ground, sky cost and best mean (bits) of
+                            // every row, for the two-column recurrence only
 };
 
 // Per-workgroup LDS of one column (S slots, W waves).
@@ -77,6 +79,193 @@ __device__ __forceinline__ void pack_record(int vb, int vt, int cls, int f, floa
 // a[c] for a class index known only at run time, without indexable memory
 __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
     return c == 0 ? a0 : (c == 1 ? a1 : a2);
+}
+
+// Backtracking of one column (Sec. 3.3, Sec. 4.4) by one wave64: every
+// row's final object, ground and sky cost and best object mean are in LDS
+// (L.crow_*), its prefix values in the column's tables (in).
+template <int S, class Lds>
+__device__ void backtrack_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
+                                 const ColumnOut& out, const Lds& L) {
+    const int lane = threadIdx.x & 63;
+    const int stride = H + 1;
+    const uint32_t stride4 = (uint32_t)stride * 4u;
+    const int fbase = in.fbase;
+    const int nrow = in.fmax - fbase + 1;
+    const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
+    const auto pgr = make_rsrc(in.PG, stride4);
+    const auto psr = make_rsrc(in.PS, stride4);
+    const auto par = make_rsrc(in.PA, stride4);
+    const auto pnr = make_rsrc(in.PN2, stride4);
+    const float eps = P.mean_eps;
+    const float INF = inf_f();
+
+    const int ktop = H - 1;
+    float total = L.crow_o[ktop];
+    int ctop = 0;
+    {
+        const float g = L.crow_g[ktop], sk = L.crow_s[ktop];
+        if (g < total) { total = g; ctop = 1; }
+        if (sk < total) { total = sk; ctop = 2; }
+    }
+
+    // Walk the links from the top.  direct = false keeps the first 64
+    // stixels in lane registers (stixel t in lane t) and only counts the
+    // rest; direct = true writes every stixel straight to its bottom-up
+    // position (second pass, needed only for more than 64 stixels).
+    auto walk = [&](bool direct, int n_total, RecRegs& rr) -> int {
+        int k = ktop, cls = ctop, t = 0;
+        float target = total;
+        while (true) {
+            const float kG = (k <= vtop) ? buf_load(pgr, k + 1) : INF;
+            const float kS = buf_load(psr, k + 1);
+            const float kA = buf_load(par, k + 1), kN = buf_load(pnr, k + 1);
+            const int kk = k + 1;
+            int lb = -1, lc = -1, lf = 0;
+            float prevC = 0.0f;
+            // priors of the three predecessor classes into class cls
+            const float tO = pick3(P.trans[0][0], P.trans[0][1], P.trans[0][2], cls);
+            const float tG = pick3(P.trans[1][0], P.trans[1][1], P.trans[1][2], cls);
+            const float tS = pick3(P.trans[2][0], P.trans[2][1], P.trans[2][2], cls);
+            {   // bottom stixel b = 0 (prefix entries at 0 are zero)
+                int f0 = 0;
+                float d0;
+                if (cls == 0) {
+                    f0 = rounded_mean(kA, kN, eps);
+                    d0 = buf_load(po, (f0 - fbase) * stride + kk);
+                } else {
+                    d0 = (cls == 1) ? kG : kS;
+                }
+                if (d0 + pick3(P.first[0], P.first[1], P.first[2], cls) == target) {
+                    lb = 0;
+                    lf = f0;
+                }
+            }
+            // The slots holding predecessor rows p < k go in groups: a group's
+            // prefix loads are issued together, then its table gathers, then
+            // its candidates are checked in b order (lanes past the row form
+            // out-of-range indices, which the buffer bounds checks read as 0).
+            constexpr int BG = (S <= 4) ? S : 4;
+            const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
+            const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
+            for (int g0 = 0; g0 < S; g0 += BG) {
+                if (lb >= 0 || g0 * 64 >= k) break;
+                float pa[BG], pn[BG], dk[BG], db[BG];
+                int fv[BG], thi[BG], tlo[BG];
+#pragma unroll
+                for (int i = 0; i < BG; ++i) {
+                    const int s = g0 + i;
+                    if (s >= S || s * 64 >= k) break;
+                    const int bb = s * 64 + lane + 1;
+                    if (cls == 0) {
+                        pa[i] = buf_load(par, bb);
+                        pn[i] = buf_load(pnr, bb);
+                    } else {
+                        pa[i] = buf_load((cls == 1) ? pgr : psr, bb);
+                    }
+                }
+                if (cls == 0) {
+#pragma unroll
+                    for (int i = 0; i < BG; ++i) {
+                        const int s = g0 + i;
+                        if (s >= S || s * 64 >= k) break;
+                        const int p = s * 64 + lane, bb = p + 1;
+                        const int f = rounded_mean(kA - pa[i], kN - pn[i], eps);
+                        fv[i] = f;
+                        dk[i] = buf_load(po, (f - fbase) * stride + kk);
+                        db[i] = buf_load(po, (f - fbase) * stride + bb);
+                        const int r = (p < k) ? H - 1 - bb : 0;
+                        thi[i] = __builtin_bit_cast(int, buf_load(fgh, r));
+                        tlo[i] = __builtin_bit_cast(int, buf_load(fgl, r));
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < BG; ++i) {
+                    const int s = g0 + i;
+                    if (s >= S || s * 64 >= k) break;
+                    const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
+                    const bool inr = p < k;
+                    float data;
+                    int f = 0;
+                    float pen_o = 0.0f, pen_g = 0.0f;
+                    const float mo = L.crow_o[p], mg = L.crow_g[p], ms = L.crow_s[p];   // p < 64 S
+                    if (cls == 0) {
+                        f = fv[i];
+                        data = dk[i] - db[i];
+                        pen_o = (f > (int)L.crow_f[p] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
+                        pen_g = (f > thi[i]) ? P.c_dive : ((f < tlo[i]) ? P.c_grav : 0.0f);
+                    } else {
+                        // ground stixels end at or below vtop, so PG[p+1] is finite
+                        data = ((cls == 1) ? kG : kS) - pa[i];
+                    }
+                    const float co = mo + tO + pen_o + data;
+                    const float cg = mg + tG + pen_g + data;
+                    const float cs = ms + tS + data;
+                    const int code = !inr ? 3
+                                   : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
+                    const uint64_t m = __ballot(code < 3);
+                    if (m) {
+                        const int l0 = (int)__builtin_ctzll(m);
+                        lb = s * 64 + l0 + 1;
+                        lc = readlane_i(code, l0);
+                        lf = readlane_i(f, l0);
+                        const float pc = (lc == 0) ? mo : ((lc == 1) ? mg : ms);
+                        prevC = readlane_f(pc, l0);
+                        break;
+                    }
+                }
+            }
+            if (lb < 0) return -1;
+            const float cost = (lb > 0) ? target - prevC : target;
+            const int fout = (cls == 0) ? lf : 0;
+            if (!direct) {
+                if (lane == t) pack_record(lb, k, cls, fout, cost, rr.w0, rr.w1, rr.w2);
+            } else {
+                const int pos = n_total - 1 - t;
+                if (pos < out.cap && lane == 0) {
+                    uint32_t w0, w1;
+                    float w2;
+                    pack_record(lb, k, cls, fout, cost, w0, w1, w2);
+                    out.rec[pos * 3 + 0] = w0;
+                    out.rec[pos * 3 + 1] = w1;
+                    out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, w2);
+                }
+            }
+            ++t;
+            if (lb == 0) break;
+            k = lb - 1;
+            cls = lc;
+            target = prevC;
+        }
+        return t;
+    };
+
+    RecRegs rr{0u, 0u, 0.0f};
+    const int n = walk(false, 0, rr);
+    if (n < 0) {
+        if (lane == 0) {
+            *out.count = 0;
+            *out.total = total;
+            *out.overflow = 255;
+        }
+        return;
+    }
+    if (n <= 64) {
+        const int pos = n - 1 - lane;
+        if (lane < n && pos < out.cap) {
+            out.rec[pos * 3 + 0] = rr.w0;
+            out.rec[pos * 3 + 1] = rr.w1;
+            out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, rr.w2);
+        }
+    } else {
+        RecRegs dummy{0u, 0u, 0.0f};
+        walk(true, n, dummy);
+    }
+    if (lane == 0) {
+        *out.count = n < out.cap ? n : out.cap;
+        *out.total = total;
+        *out.overflow = (uint8_t)(n > out.cap ? 1 : 0);
+    }
 }
 
 // S: 64-row slots (h <= 64 S); NCH: 64-entry chunks of disparity rows
@@ -375,174 +564,234 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     __syncthreads();
     if (wave != 0) return;
 
-    // ---------------------------------------------------------- backtracking
-    // (wave 0; every row's final costs are in LDS, its prefix values in the
-    // column's tables)
-    const int ktop = H - 1;
-    float total = L.crow_o[ktop];
-    int ctop = 0;
-    {
-        const float g = L.crow_g[ktop], sk = L.crow_s[ktop];
-        if (g < total) { total = g; ctop = 1; }
-        if (sk < total) { total = sk; ctop = 2; }
+    backtrack_column<S>(H, vtop, P, in, out, L);
+}
+
+
+// Two columns of one frame per wave64 (same height, same camera model): the
+// lanes of half X = lane / 32 take column X, and lane l of that half owns
+// rows k = 32 s + l for 32-row slots s < 2 S.  Every per-step operation of
+// solve_column (the row broadcast, the prior table, the running minima, the
+// prefetch) then serves two columns at once.  The two columns' tables lie
+// one column stride apart (in1.X = in0.X + the stride for every table, PO
+// after eight (h+1) arrays: PG, PS, PA, PN and the four row-cost arrays).
+// has1: the second column exists (a frame with an odd column count leaves
+// the last pair's second half idle; its results are not written).
+// qs2: the two columns' reduced pixels in LDS, [2][64 S].
+template <int S, int NCH>
+__device__ void solve_pair(const int H, const int vtop, const Prior P, const ColumnIn& in0,
+                           const ColumnIn& in1, const ColumnOut& out0, const ColumnOut& out1,
+                           const bool has1, const int16_t* qs2, float* qtab2,
+                           ColumnLds<S, 1>& L) {
+    constexpr int S2 = 2 * S;                        // 32-row slots
+    constexpr int NC = 2 * NCH;                      // 32-entry disparity chunks
+    const int lane = threadIdx.x & 63;
+    const int X = lane >> 5, l = lane & 31;
+    const int stride = H + 1;
+    const uint32_t stride4 = (uint32_t)stride * 4u;
+    const uint32_t colstride4 = (uint32_t)(in1.PG - in0.PG) * 4u;
+    const uint32_t cb = X ? colstride4 : 0u;         // this half's column base (bytes)
+    const auto tab = make_rsrc(in0.PG, 2u * colstride4);
+    const uint32_t oPG = cb, oPS = cb + stride4, oPA = cb + 2u * stride4, oPN = cb + 3u * stride4;
+    const uint32_t oRO = cb + 4u * stride4, oRG = cb + 5u * stride4, oRS = cb + 6u * stride4,
+                   oRF = cb + 7u * stride4, oPO = cb + 8u * stride4;
+    const int fbase = X ? in1.fbase : in0.fbase;
+    const int nrow = (X ? in1.fmax : in0.fmax) - fbase + 1;
+    // 32-entry chunks of disparity rows that either column needs
+    const int nchunk = max(__builtin_amdgcn_readlane((nrow + 31) >> 5, 0),
+                           __builtin_amdgcn_readlane((nrow + 31) >> 5, 32));
+    const float eps = P.mean_eps;
+    const float cmean = eps - (float)fbase;
+    const float INF = inf_f();
+    const uint32_t lanek4 = oPO + (uint32_t)(l + 1) * 4u;   // PO row offset of k+1 within slot 0
+    float* const qtab = qtab2 + X * 256;
+
+    float eA[S2], eN[S2], mO[S2];
+    int fO[S2];
+    const int nslots = (H + 31) >> 5;
+
+#pragma unroll
+    for (int t = 0; t < S2; ++t) {
+        if (t >= nslots) {
+            mO[t] = INF;
+            eA[t] = eN[t] = 0.0f;
+            fO[t] = 0;
+            continue;
+        }
+        const int k = t * 32 + l;
+        const int kk = min(k + 1, H);
+        eA[t] = buf_load_b(tab, oPA + (uint32_t)kk * 4u, 0u);
+        eN[t] = buf_load_b(tab, oPN + (uint32_t)kk * 4u, 0u);
+        const int fi = mean_index(eA[t], eN[t], cmean);
+        mO[t] = buf_load_b(tab, oPO + __umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0u) +
+                P.first[0];
+        fO[t] = fi;
     }
 
-    // Walk the links from the top.  direct = false keeps the first 64
-    // stixels in lane registers (stixel t in lane t) and only counts the
-    // rest; direct = true writes every stixel straight to its bottom-up
-    // position (second pass, needed only for more than 64 stixels).
-    auto walk = [&](bool direct, int n_total, RecRegs& rr) -> int {
-        int k = ktop, cls = ctop, t = 0;
-        float target = total;
-        while (true) {
-            const float kG = (k <= vtop) ? buf_load(pgr, k + 1) : INF;
-            const float kS = buf_load(psr, k + 1);
-            const float kA = buf_load(par, k + 1), kN = buf_load(pnr, k + 1);
-            const int kk = k + 1;
-            int lb = -1, lc = -1, lf = 0;
-            float prevC = 0.0f;
-            // priors of the three predecessor classes into class cls
-            const float tO = pick3(P.trans[0][0], P.trans[0][1], P.trans[0][2], cls);
-            const float tG = pick3(P.trans[1][0], P.trans[1][1], P.trans[1][2], cls);
-            const float tS = pick3(P.trans[2][0], P.trans[2][1], P.trans[2][2], cls);
-            {   // bottom stixel b = 0 (prefix entries at 0 are zero)
-                int f0 = 0;
-                float d0;
-                if (cls == 0) {
-                    f0 = rounded_mean(kA, kN, eps);
-                    d0 = buf_load(po, (f0 - fbase) * stride + kk);
-                } else {
-                    d0 = (cls == 1) ? kG : kS;
-                }
-                if (d0 + pick3(P.first[0], P.first[1], P.first[2], cls) == target) {
-                    lb = 0;
-                    lf = f0;
-                }
-            }
-            // The slots holding predecessor rows p < k go in groups: a group's
-            // prefix loads are issued together, then its table gathers, then
-            // its candidates are checked in b order (lanes past the row form
-            // out-of-range indices, which the buffer bounds checks read as 0).
-            constexpr int BG = (S <= 4) ? S : 4;
-            const auto fgh = make_rsrc(in.fg_hi, (uint32_t)H * 4u);
-            const auto fgl = make_rsrc(in.fg_lo, (uint32_t)H * 4u);
-            for (int g0 = 0; g0 < S; g0 += BG) {
-                if (lb >= 0 || g0 * 64 >= k) break;
-                float pa[BG], pn[BG], dk[BG], db[BG];
-                int fv[BG], thi[BG], tlo[BG];
+    float pcol[NC], orow[NC];
+    uint32_t roff[NC];
 #pragma unroll
-                for (int i = 0; i < BG; ++i) {
-                    const int s = g0 + i;
-                    if (s >= S || s * 64 >= k) break;
-                    const int bb = s * 64 + lane + 1;
-                    if (cls == 0) {
-                        pa[i] = buf_load(par, bb);
-                        pn[i] = buf_load(pnr, bb);
-                    } else {
-                        pa[i] = buf_load((cls == 1) ? pgr : psr, bb);
-                    }
-                }
-                if (cls == 0) {
+    for (int c = 0; c < NC; ++c) {
+        const int i = 32 * c + l;
+        roff[c] = (i < nrow) ? (uint32_t)(fbase + i) * 4u : 0x40000000u;
+        pcol[c] = orow[c] = 0.0f;
+    }
+    int thi_n = 0, tlo_n = 0;
+    float ps_n = 0.0f, pg_n = INF;
+    const auto odf = make_rsrc(in0.O_df, (uint32_t)(in0.D * in0.D) * 4u);
+    const auto fgh = make_rsrc(in0.fg_hi, (uint32_t)H * 4u);
+    const auto fgl = make_rsrc(in0.fg_lo, (uint32_t)H * 4u);
+    auto load_next = [&](int v) {
+        const int qv = qs2[X * 64 * S + v];
+        const uint32_t qoff = (qv >= 0) ? (uint32_t)(qv * in0.D) * 4u : 0x40000000u;
 #pragma unroll
-                    for (int i = 0; i < BG; ++i) {
-                        const int s = g0 + i;
-                        if (s >= S || s * 64 >= k) break;
-                        const int p = s * 64 + lane, bb = p + 1;
-                        const int f = rounded_mean(kA - pa[i], kN - pn[i], eps);
-                        fv[i] = f;
-                        dk[i] = buf_load(po, (f - fbase) * stride + kk);
-                        db[i] = buf_load(po, (f - fbase) * stride + bb);
-                        const int r = (p < k) ? H - 1 - bb : 0;
-                        thi[i] = __builtin_bit_cast(int, buf_load(fgh, r));
-                        tlo[i] = __builtin_bit_cast(int, buf_load(fgl, r));
-                    }
-                }
+        for (int c = 0; c < NC; ++c) orow[c] = buf_load_b(odf, roff[c] + qoff, 0u);
+        ps_n = buf_load_b(tab, oPS + (uint32_t)(v + 1) * 4u, 0u);
+        const float pg = buf_load_b(tab, oPG + (uint32_t)(v + 1) * 4u, 0u);
+        pg_n = (v <= vtop) ? pg : INF;
+        thi_n = __builtin_bit_cast(int, buf_load(fgh, H - 2 - v));
+        tlo_n = __builtin_bit_cast(int, buf_load(fgl, H - 2 - v));
+    };
+    if (H > 1) load_next(0);
+
+    float RG = P.first[1], RS = P.first[2];   // running minima (separable ground and sky terms)
+
+    // one step: row j = 32 sj + jl of both columns is final; fold the stixels
+    // starting at b = j + 1 into the rows k > j
+    auto step = [&](auto gr_tag, const int sj, const int jl) {
+        constexpr bool GR = decltype(gr_tag)::value;
+        const int j = sj * 32 + jl, b = j + 1;
+        float Co = 0.0f, bA = 0.0f, bN = 0.0f;
+        int fp = 0;
 #pragma unroll
-                for (int i = 0; i < BG; ++i) {
-                    const int s = g0 + i;
-                    if (s >= S || s * 64 >= k) break;
-                    const int p = s * 64 + lane;     // predecessor row, cut at b = p+1
-                    const bool inr = p < k;
-                    float data;
-                    int f = 0;
-                    float pen_o = 0.0f, pen_g = 0.0f;
-                    const float mo = L.crow_o[p], mg = L.crow_g[p], ms = L.crow_s[p];   // p < 64 S
-                    if (cls == 0) {
-                        f = fv[i];
-                        data = dk[i] - db[i];
-                        pen_o = (f > (int)L.crow_f[p] + fbase + P.tau_ord) ? P.c_ord : 0.0f;
-                        pen_g = (f > thi[i]) ? P.c_dive : ((f < tlo[i]) ? P.c_grav : 0.0f);
-                    } else {
-                        // ground stixels end at or below vtop, so PG[p+1] is finite
-                        data = ((cls == 1) ? kG : kS) - pa[i];
-                    }
-                    const float co = mo + tO + pen_o + data;
-                    const float cg = mg + tG + pen_g + data;
-                    const float cs = ms + tS + data;
-                    const int code = !inr ? 3
-                                   : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
-                    const uint64_t m = __ballot(code < 3);
-                    if (m) {
-                        const int l0 = (int)__builtin_ctzll(m);
-                        lb = s * 64 + l0 + 1;
-                        lc = readlane_i(code, l0);
-                        lf = readlane_i(f, l0);
-                        const float pc = (lc == 0) ? mo : ((lc == 1) ? mg : ms);
-                        prevC = readlane_f(pc, l0);
-                        break;
-                    }
-                }
+        for (int t = 0; t < S2; ++t) {
+            if (t == sj) {
+                const float c0 = readlane_f(mO[t], jl), c1 = readlane_f(mO[t], jl + 32);
+                const int f0 = readlane_i(fO[t], jl), f1 = readlane_i(fO[t], jl + 32);
+                const float a0 = readlane_f(eA[t], jl), a1 = readlane_f(eA[t], jl + 32);
+                const float n0 = readlane_f(eN[t], jl), n1 = readlane_f(eN[t], jl + 32);
+                Co = X ? c1 : c0;
+                fp = X ? f1 : f0;
+                bA = X ? a1 : a0;
+                bN = X ? n1 : n0;
             }
-            if (lb < 0) return -1;
-            const float cost = (lb > 0) ? target - prevC : target;
-            const int fout = (cls == 0) ? lf : 0;
-            if (!direct) {
-                if (lane == t) pack_record(lb, k, cls, fout, cost, rr.w0, rr.w1, rr.w2);
-            } else {
-                const int pos = n_total - 1 - t;
-                if (pos < out.cap && lane == 0) {
-                    uint32_t w0, w1;
-                    float w2;
-                    pack_record(lb, k, cls, fout, cost, w0, w1, w2);
-                    out.rec[pos * 3 + 0] = w0;
-                    out.rec[pos * 3 + 1] = w1;
-                    out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, w2);
-                }
-            }
-            ++t;
-            if (lb == 0) break;
-            k = lb - 1;
-            cls = lc;
-            target = prevC;
         }
-        return t;
+        const float bS = ps_n, bG = pg_n;
+        const float Cg = bG + RG, Cs = bS + RS;
+        if (l == 0) {   // row j's ground and sky costs, for the backtracking
+            buf_store_b(tab, Cg, oRG + (uint32_t)j * 4u, 0u);
+            buf_store_b(tab, Cs, oRS + (uint32_t)j * 4u, 0u);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pcol[c] += orow[c];
+        const int thi = thi_n, tlo = tlo_n;
+        load_next(b);
+
+        const float XS =
+            vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+        RS = vmin(RS, XS);
+        const float Xoo = Co + P.trans[0][0];
+        const float Xoo_p = Xoo + P.c_ord;
+        const int tord = fp + fbase + P.tau_ord;
+        const float Xso = Cs + P.trans[2][0];
+        float Xgo = INF, Xgo_d = INF, Xgo_g = INF;
+        if constexpr (GR) {
+            const float XG = (b <= vtop)
+                ? vmin(vmin(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
+                : INF;
+            RG = vmin(RG, XG);
+            Xgo = Cg + P.trans[1][0];
+            Xgo_d = Xgo + P.c_dive;
+            Xgo_g = Xgo + P.c_grav;
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= nchunk) break;
+            const int f = fbase + 32 * c + l;
+            const float v1 = (f > tord) ? Xoo_p : Xoo;
+            float pr;
+            if constexpr (GR) {
+                float v2 = (f < tlo) ? Xgo_g : Xgo;
+                v2 = (f > thi) ? Xgo_d : v2;
+                pr = vmin(vmin(v1, v2), Xso);
+            } else {
+                pr = vmin(v1, Xso);
+            }
+            qtab[32 * c + l] = pr - pcol[c];
+        }
+
+        float pk[S2], qv[S2];
+        int fS[S2];
+        constexpr int G = (S2 <= 8) ? S2 : 8;
+#pragma unroll
+        for (int g0 = 0; g0 < S2; g0 += G) {
+            if (g0 >= nslots) break;
+            if (g0 + G <= sj) continue;
+#pragma unroll
+            for (int t = g0; t < g0 + G && t < S2; ++t) {
+                if (t < sj) continue;
+                const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
+                pk[t] = buf_load_b(tab, __umul24(fi, stride4) + lanek4, (uint32_t)(t * 128));
+                qv[t] = qtab[fi & 255u];
+                fS[t] = (int)fi;
+            }
+#pragma unroll
+            for (int t = g0; t < g0 + G && t < S2; ++t) {
+                if (t < sj) continue;
+                const bool act = (t > sj) || (l > jl);
+                float cO = qv[t] + pk[t];
+                cO = act ? cO : INF;
+                const bool better = cO < mO[t];
+                mO[t] = better ? cO : mO[t];
+                fO[t] = better ? fS[t] : fO[t];
+            }
+        }
     };
 
-    RecRegs rr{0u, 0u, 0.0f};
-    const int n = walk(false, 0, rr);
-    if (n < 0) {
-        if (lane == 0) {
-            *out.count = 0;
-            *out.total = total;
-            *out.overflow = 255;
-        }
-        return;
+    // unrolled over the 32-row slot of row j, so that every slot test is
+    // decided at compile time
+#pragma unroll
+    for (int sj = 0; sj < S2; ++sj) {
+        const int jend = min(32, H - 1 - sj * 32);
+        const int jgr = min(jend, max(0, vtop + 1 - sj * 32));
+        for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl);
+        for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl);
     }
-    if (n <= 64) {
-        const int pos = n - 1 - lane;
-        if (lane < n && pos < out.cap) {
-            out.rec[pos * 3 + 0] = rr.w0;
-            out.rec[pos * 3 + 1] = rr.w1;
-            out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, rr.w2);
-        }
-    } else {
-        RecRegs dummy{0u, 0u, 0.0f};
-        walk(true, n, dummy);
+
+    // the top rows' ground and sky costs, and every row's object cost and
+    // best mean, into the row-cost arrays
+    if (l == 0) {
+        const float pg = buf_load_b(tab, oPG + (uint32_t)H * 4u, 0u);
+        buf_store_b(tab, ((H - 1 <= vtop) ? pg : INF) + RG, oRG + (uint32_t)(H - 1) * 4u, 0u);
+        buf_store_b(tab, buf_load_b(tab, oPS + (uint32_t)H * 4u, 0u) + RS,
+                    oRS + (uint32_t)(H - 1) * 4u, 0u);
     }
-    if (lane == 0) {
-        *out.count = n < out.cap ? n : out.cap;
-        *out.total = total;
-        *out.overflow = (uint8_t)(n > out.cap ? 1 : 0);
+#pragma unroll
+    for (int t = 0; t < S2; ++t) {
+        const int k = t * 32 + l;
+        if (t < nslots && k < H) {
+            buf_store_b(tab, mO[t], oRO + (uint32_t)k * 4u, 0u);
+            buf_store_b(tab, __builtin_bit_cast(float, fO[t]), oRF + (uint32_t)k * 4u, 0u);
+        }
+    }
+
+    // backtracking, one column at a time over the whole wave, from LDS copies
+    // of the row costs (the barrier orders the stores above before the loads
+    // below, which other lanes make)
+    __syncthreads();
+    for (int x = 0; x < 2; ++x) {
+        if (x == 1 && !has1) break;
+        const ColumnIn& in = x ? in1 : in0;
+        const float* rc = in.rowc;
+        for (int k = lane; k < H; k += 64) {
+            L.crow_o[k] = rc[k];
+            L.crow_g[k] = rc[stride + k];
+            L.crow_s[k] = rc[2 * stride + k];
+            L.crow_f[k] = (uint8_t)__builtin_bit_cast(int, rc[3 * stride + k]);
+        }
+        __syncthreads();
+        backtrack_column<S>(H, vtop, P, in, x ? out1 : out0, L);
+        __syncthreads();
     }
 }
 

@@ -52,6 +52,10 @@ __host__ __device__ constexpr int kernel_chunks(int d_range) { return d_range <=
     X(10, 4, 2) X(10, 4, 4) X(12, 4, 1) X(12, 4, 2) X(12, 4, 4) X(14, 4, 1) X(14, 4, 2) \
     X(14, 4, 4) X(16, 4, 1) X(16, 4, 2) X(16, 4, 4)
 
+// Slot counts of the two-columns-per-wave recurrence (d_range <= 128, h <= 512).
+#define STX_FOR_EACH_PAIR_VARIANT(X) \
+    X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2)
+
 // Quantised prior constants of one camera model, in FP32 (exact on the grid).
 struct Prior {
     float first[3];       // F[c] + beta

@@ -21,14 +21,16 @@ def frame_setup(n, seeds=None):
     return p, h, frames
 
 
-def run_batch(items, workgroups=0, max_h=440, max_d=128, waves=1):
+def run_batch(items, workgroups=0, max_h=440, max_d=128, waves=1, columns=1):
     import torch
     b = P.Batch(len(items), sum(h.num_columns(d.shape[1]) for h, d, _ in items), max_h, max_d,
                 workgroups)
     b.set_waves(waves)
+    b.set_columns(columns)
     b.compute(items)
     torch.cuda.synchronize()
     assert b.waves() == waves
+    assert b.columns() == columns
     return b
 
 
@@ -76,6 +78,42 @@ def test_batch_mean_reduction_matches_oracle():
         assert_frames_equal(outs[i].to_host(), oracle.frame(p, frames[i]), f"mean frame {i}")
     for i, f in enumerate(frames):
         assert_frames_equal(outs[i].to_host(), gpu_frame(h, f), f"mean batch vs per-frame {i}")
+
+
+def test_batch_two_columns_per_wave_matches_per_frame():
+    """Two columns of a frame per wave64 (one per 32-lane half): bitwise equal
+    to the per-frame path, with even (204) and odd (341) column counts."""
+    announce("batch two columns per wave")
+    p, h, frames = frame_setup(12)
+    outs = [h.new_output(1024, 440) for _ in frames]
+    run_batch([(h, to_device(f), o) for f, o in zip(frames, outs)], columns=2)
+    for i, f in enumerate(frames):
+        assert_frames_equal(outs[i].to_host(), gpu_frame(h, f), f"pairs frame {i}")
+    assert_frames_equal(outs[7].to_host(), oracle.frame(p, frames[7]), "pairs oracle frame 7")
+    p3 = synth.make_params(stixel_width=3)
+    h3 = P.Stixels(p3)
+    outs3 = [h3.new_output(1024, 440) for _ in frames[:4]]
+    run_batch([(h3, to_device(f), o) for f, o in zip(frames[:4], outs3)], columns=2)
+    for i, f in enumerate(frames[:4]):
+        assert h3.num_columns(1024) % 2 == 1
+        assert_frames_equal(outs3[i].to_host(), oracle.frame(p3, f), f"pairs s=3 frame {i}")
+
+
+@pytest.mark.parametrize("H", [1, 31, 32, 33, 63, 64, 65, 95, 129, 257, 300, 511, 512])
+def test_batch_two_columns_per_wave_heights(H):
+    """Heights around the 32-row slot boundaries, adversarial columns, odd
+    and even column counts."""
+    announce(f"pairs height {H}")
+    W = 5 * (7 + H % 4)
+    cam = dict(synth.CAMERA_1024x440, horizon_row=float((H * 7) // 10))
+    p = synth.make_params(camera=cam, stixel_width=5, max_disparity=128, max_width=W,
+                          max_height=H)
+    h = P.Stixels(p)
+    disps = [synth.random_columns_frame(100 + H + i, W, H, 128) for i in range(3)]
+    outs = [h.new_output(W, H) for _ in disps]
+    run_batch([(h, to_device(d), o) for d, o in zip(disps, outs)], max_h=H, columns=2)
+    for i, d in enumerate(disps):
+        assert_frames_equal(outs[i].to_host(), oracle.frame(p, d), f"pairs H={H} frame {i}")
 
 
 def uneven_items(n):

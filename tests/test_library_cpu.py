@@ -167,6 +167,8 @@ def test_create_and_batch_reject_bad_arguments_without_a_device():
     assert L.stixels_set_po_placement(None, 1) == B.E_INVALID_ARG
     assert L.stixels_batch_set_waves(None, 2) == B.E_INVALID_ARG
     assert L.stixels_batch_waves(None) == 0
+    assert L.stixels_batch_set_columns(None, 2) == B.E_INVALID_ARG
+    assert L.stixels_batch_columns(None) == 0
     assert L.stixels_selftest_mean(1, 10, None) == B.E_INVALID_ARG
     n = C.c_int64()
     assert L.stixels_selftest_mean(256, 8192, C.byref(n)) == B.E_INVALID_ARG
