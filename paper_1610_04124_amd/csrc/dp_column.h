@@ -359,32 +359,40 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     uint32_t roff[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) roff[c] = row_off(c);
-    auto load_next = [&](int v) {
-        // for step v: object costs of pixel q_v for every disparity row, the
-        // sky and ground prefixes at v+1 (ground INF above vtop) and the
-        // bounds of the base row v+1 (top-down row H-2-v).  Straight-line
-        // code: every index either lies inside its table or falls past the
-        // end of its buffer resource, which reads 0 (v <= H-1 gives
-        // top-down row >= -1; an invalid pixel or a disparity row past the
-        // column's range gives index -1).
-        const int qv = in.q[v];
-        // byte offset of O[qv][fbase + i]: a wave-uniform part plus a
+    // The pixels the steps of slot sj load ahead, q_v for v = 64 sj + lane
+    // + 1, read from LDS once per slot (short columns); a step takes its
+    // own with readlane, so that the pixel is wave-uniform (scalar
+    // registers) and no LDS round trip sits in the step.
+    auto q_block = [&](int sj) -> int {
+        const int v = 64 * sj + lane + 1;
+        return (v < H) ? (int)in.q[v] : -1;
+    };
+    auto load_next = [&](int v, int qv) {
+        // for step v (qv = q_v): object costs of pixel q_v for every
+        // disparity row, the sky and ground prefixes at v+1 (ground INF
+        // above vtop) and the bounds of the base row v+1 (top-down row
+        // H-2-v).  Straight-line code: every index either lies inside its
+        // table or falls past the end of its buffer resource, which reads 0
+        // (v <= H-1 gives top-down row >= -1; an invalid pixel or a
+        // disparity row past the column's range gives index -1).
+        // Byte offset of O[qv][fbase + i]: a wave-uniform part plus a
         // per-lane part; an invalid pixel or a disparity row past the
         // column's range adds 2^30, far past the end of the resource (in the
         // per-lane offset, which the bounds check always covers)
-        const uint32_t qoff = (qv >= 0) ? (uint32_t)(qv * in.D) * 4u : 0x40000000u;
+        const uint32_t qoff = (qv >= 0) ? (uint32_t)__umul24(qv, in.D) * 4u : 0x40000000u;
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
             orow[c] = buf_load_b(odf, ((NCH <= 2) ? roff[c] : row_off(c)) + qoff, 0u);
-        ps_n = buf_load(psr, v + 1);
-        const float pg = buf_load(pgr, v + 1);
+        // v + 1 <= H: inside the prefix tables, so the offset may be scalar
+        ps_n = buf_load_b(psr, 0u, (uint32_t)(v + 1) * 4u);
+        const float pg = buf_load_b(pgr, 0u, (uint32_t)(v + 1) * 4u);
         pg_n = (v <= vtop) ? pg : INF;
         thi_n = __builtin_bit_cast(int, buf_load(fgh, H - 2 - v));
         tlo_n = __builtin_bit_cast(int, buf_load(fgl, H - 2 - v));
     };
 #pragma unroll
     for (int c = 0; c < NCH; ++c) pcol[c] = orow[c] = 0.0f;
-    if (H > 1) load_next(0);
+    if (H > 1) load_next(0, __builtin_amdgcn_readfirstlane((int)in.q[0]));
 
     // The ground and sky data terms of a stixel [b, k] are prefix
     // differences whose b-side does not depend on k, and their priors depend
@@ -404,7 +412,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // issued before any candidate is folded.  Steps where no ground stixel
     // can end at or below b-1 (b > vtop+1) skip the ground terms.  Slots
     // below the current row are skipped by uniform branches.
-    auto step = [&](auto gr_tag, const int sj, const int jl) {
+    auto step = [&](auto gr_tag, const int sj, const int jl, const int qblk) {
         constexpr bool GR = decltype(gr_tag)::value;
         const int j = sj * 64 + jl, b = j + 1;
         // row j's object cost, mean and prefix values, read from its owning
@@ -442,6 +450,56 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             bA = bc[2];
             bN = bc[3];
         }
+        // With two disparity chunks and up to eight slots, the gathers of
+        // every open slot are issued first (they depend on row j's prefix
+        // values only, not on its costs), so that their latency overlaps the
+        // prior table; elsewhere the registers this holds across the table
+        // build spill (measured slower), and each group is gathered and
+        // folded after it.  Slots of a group that lie past the column's height
+        // fold values into rows that are never read (their gathers stay
+        // inside the column's table or read 0 past its end, and their table
+        // index is masked): skipping them one by one would cost more than
+        // the work.  Groups bound the registers a tall column holds.
+        constexpr int G = (SW <= 8) ? SW : 4;
+        constexpr bool EARLY = (NCH == 2) && (S <= 8);
+        float pk[SW];
+        int fS[SW];
+        auto gather = [&](int g0) {
+#pragma unroll
+            for (int t = g0; t < g0 + G && t < SW; ++t) {
+                const int s = t * W + wave;
+                if (s < sj) continue;
+                const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
+                pk[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
+                fS[t] = (int)fi;
+            }
+        };
+        auto fold = [&](int g0) {
+            float qv[SW];
+#pragma unroll
+            for (int t = g0; t < g0 + G && t < SW; ++t) {
+                if (t * W + wave < sj) continue;
+                qv[t] = qtab[(uint32_t)fS[t] & 255u];   // < 64 NCH except in rows past H
+            }
+#pragma unroll
+            for (int t = g0; t < g0 + G && t < SW; ++t) {
+                const int s = t * W + wave;
+                if (s < sj) continue;
+                const bool act = (s > sj) || (lane > jl);          // rows k > j only
+                float cO = qv[t] + pk[t];
+                cO = act ? cO : INF;
+                const bool better = cO < mO[t];
+                mO[t] = better ? cO : mO[t];
+                fO[t] = better ? fS[t] : fO[t];
+            }
+        };
+        auto group_open = [&](int g0) {
+            return g0 * W < nslots && (g0 + G - 1) * W + wave >= sj;
+        };
+        if constexpr (EARLY) {
+            if (group_open(0)) gather(0);
+        }
+
         // row j's ground and sky costs (ground is INF above vtop: bG is),
         // recorded for the backtracking
         const float bS = ps_n, bG = pg_n;
@@ -453,7 +511,9 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
         for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
         const int thi = thi_n, tlo = tlo_n;                   // bounds at base row b
-        load_next(b);                                         // pixel q_{j+1}, base b+1 (b <= H-1)
+        // pixel q_{j+1}, base b+1 (b <= H-1); tall columns read the pixel
+        // from LDS (a register held across their runtime loop spills)
+        load_next(b, (S <= 8) ? readlane_i(qblk, jl) : (int)in.q[b]);
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
@@ -490,38 +550,15 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             qtab[64 * c + lane] = pr - pcol[c];
         }
 
-        float pk[SW], qv[SW];
-        int fS[SW];
-        // gathers of a group of slots are in flight together; groups bound
-        // the registers they hold for tall columns.  Slots of a group that
-        // lie past the column's height fold values into rows that are never
-        // read (their gathers stay inside the column's table or read 0 past
-        // its end, and their table index is masked): skipping them one by
-        // one would cost more than the work
-        constexpr int G = (SW <= 8) ? SW : 4;
+        if constexpr (EARLY) {
+            if (group_open(0)) fold(0);
+        } else {
 #pragma unroll
-        for (int g0 = 0; g0 < SW; g0 += G) {
-            if (g0 * W >= nslots) break;
-            if ((g0 + G - 1) * W + wave < sj) continue;
-#pragma unroll
-            for (int t = g0; t < g0 + G && t < SW; ++t) {
-                const int s = t * W + wave;
-                if (s < sj) continue;
-                const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
-                pk[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
-                qv[t] = qtab[fi & 255u];               // fi < 64 NCH except in rows past H
-                fS[t] = (int)fi;
-            }
-#pragma unroll
-            for (int t = g0; t < g0 + G && t < SW; ++t) {
-                const int s = t * W + wave;
-                if (s < sj) continue;
-                const bool act = (s > sj) || (lane > jl);   // rows k > j only
-                float cO = qv[t] + pk[t];
-                cO = act ? cO : INF;
-                const bool better = cO < mO[t];
-                mO[t] = better ? cO : mO[t];
-                fO[t] = better ? fS[t] : fO[t];
+            for (int g0 = 0; g0 < SW; g0 += G) {
+                if (g0 * W >= nslots) break;
+                if (!group_open(g0)) continue;
+                gather(g0);
+                fold(g0);
             }
         }
     };
@@ -533,17 +570,19 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
         for (int sj = 0; sj < S; ++sj) {
             const int jend = min(64, H - 1 - sj * 64);
+            if (jend <= 0) break;
+            const int qblk = q_block(sj);
             // steps whose base b = sj*64+jl+1 can still follow a ground stixel
             const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
-            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl);
-            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl);
+            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, qblk);
+            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, qblk);
         }
     } else {
         // tall columns: one runtime loop keeps the code (and the registers
         // live across it) to a single copy of the step
         for (int j = 0; j < H - 1; ++j) {
-            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63);
-            else step(std::false_type{}, j >> 6, j & 63);
+            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63, 0);
+            else step(std::false_type{}, j >> 6, j & 63, 0);
         }
     }
 
