@@ -52,8 +52,9 @@ def kernel_source_hash():
 
 def traffic_from_profiles(kernel, workgroups):
     """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary, if it was taken on the current kernel sources, on the same
-    kernel variant and with the same number of workgroups."""
+    summary (one record per grid size the autotuner tries), if it was taken
+    on the current kernel sources and kernel variant and covers this number
+    of workgroups."""
     path = os.path.join(ROOT, "profiles", "batch_kernel_1024x440_b64_traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,10 +62,10 @@ def traffic_from_profiles(kernel, workgroups):
         d = json.load(open(path))
     except Exception:
         return None
-    if (d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel
-            or d.get("workgroups") != workgroups):
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel:
         return None
-    return d.get("hbm_bytes_per_launch")
+    rec = d.get("by_workgroups", {}).get(str(workgroups))
+    return rec.get("hbm_bytes_per_launch") if rec else None
 
 
 def percentile(xs, q):
