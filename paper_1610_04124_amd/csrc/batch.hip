@@ -80,8 +80,10 @@ __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch_kernel(
     const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
     unsigned int* counter, float* scratch, long long scratch_stride, int hmax) {
-    __shared__ int16_t qs[64 * S];
-    __shared__ ColumnLds<S, W> lds;
+    __shared__ ColumnLds<S, W, 64 * NCH> lds;
+    // the column's reduced pixels live in the object row-cost array, which
+    // solve_column writes only after its last read of them
+    int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
     __shared__ int task_slot;
     __shared__ int red[3][W];
     const int lane = threadIdx.x & 63;

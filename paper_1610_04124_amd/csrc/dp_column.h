@@ -44,10 +44,11 @@ struct ColumnIn {
                             // every row, for the two-column recurrence only
 };
 
-// Per-workgroup LDS of one column (S slots, W waves).
-template <int S, int W>
+// Per-workgroup LDS of one column (S slots, W waves, QT prior-table entries
+// per wave: 64 per disparity chunk).
+template <int S, int W, int QT = 256>
 struct ColumnLds {
-    float qtab[W][256];     // per wave: prior minus PO[f][b] over the disparity rows
+    float qtab[W][QT];      // per wave: prior minus PO[f][b] over the disparity rows
     float crow_g[64 * S];   // final GR^k of every row
     float crow_s[64 * S];   // final SK^k
     float crow_o[64 * S];   // final OB^k
@@ -275,7 +276,7 @@ __device__ void backtrack_column(const int H, const int vtop, const Prior P, con
 // reads in.PO).  On return the results are written.
 template <int S, int NCH, int W, bool POL = false>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out, ColumnLds<S, W>& L,
+                             const ColumnOut& out, ColumnLds<S, W, 64 * NCH>& L,
                              const float* po_lds = nullptr) {
     static_assert(W == 1 || W == 2 || W == 4, "waves per column");
     constexpr int SW = (S + W - 1) / W;              // slots per wave
@@ -359,13 +360,26 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     uint32_t roff[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) roff[c] = row_off(c);
-    // The pixels the steps of slot sj load ahead, q_v for v = 64 sj + lane
-    // + 1, read from LDS once per slot (short columns); a step takes its
-    // own with readlane, so that the pixel is wave-uniform (scalar
-    // registers) and no LDS round trip sits in the step.
-    auto q_block = [&](int sj) -> int {
-        const int v = 64 * sj + lane + 1;
-        return (v < H) ? (int)in.q[v] : -1;
+    // Short columns (S <= 8) read the wave-uniform values of the 64 steps
+    // j = 64 sj + lane of a slot once, a lane per step: the pixel q_{j+1}
+    // the step prefetches, the sky and ground prefixes at j+1 and the
+    // bounds of the base row j+1 (top-down row H-2-j).  A step takes its own
+    // with readlane (scalar registers), so per step only the object
+    // gathers and the object-cost row are vector memory instructions.
+    constexpr bool BLK = (S <= 8);
+    struct Blk {
+        int q = 0, thi = 0, tlo = 0;
+        float ps = 0.0f, pg = 0.0f;
+    };
+    auto load_block = [&](int sj) {
+        Blk k;
+        const int j = 64 * sj + lane;
+        k.q = (j + 1 < H) ? (int)in.q[j + 1] : -1;
+        k.ps = buf_load(psr, j + 1);                  // past the table: 0, never used
+        k.pg = buf_load(pgr, j + 1);
+        k.thi = __builtin_bit_cast(int, buf_load(fgh, H - 2 - j));
+        k.tlo = __builtin_bit_cast(int, buf_load(fgl, H - 2 - j));
+        return k;
     };
     auto load_next = [&](int v, int qv) {
         // for step v (qv = q_v): object costs of pixel q_v for every
@@ -383,6 +397,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
             orow[c] = buf_load_b(odf, ((NCH <= 2) ? roff[c] : row_off(c)) + qoff, 0u);
+        if constexpr (BLK) return;
         // v + 1 <= H: inside the prefix tables, so the offset may be scalar
         ps_n = buf_load_b(psr, 0u, (uint32_t)(v + 1) * 4u);
         const float pg = buf_load_b(pgr, 0u, (uint32_t)(v + 1) * 4u);
@@ -412,7 +427,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // issued before any candidate is folded.  Steps where no ground stixel
     // can end at or below b-1 (b > vtop+1) skip the ground terms.  Slots
     // below the current row are skipped by uniform branches.
-    auto step = [&](auto gr_tag, const int sj, const int jl, const int qblk) {
+    auto step = [&](auto gr_tag, const int sj, const int jl, const Blk& blk) {
         constexpr bool GR = decltype(gr_tag)::value;
         const int j = sj * 64 + jl, b = j + 1;
         // row j's object cost, mean and prefix values, read from its owning
@@ -479,7 +494,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
             for (int t = g0; t < g0 + G && t < SW; ++t) {
                 if (t * W + wave < sj) continue;
-                qv[t] = qtab[(uint32_t)fS[t] & 255u];   // < 64 NCH except in rows past H
+                // fi < 64 NCH except, possibly, in rows past H
+                qv[t] = qtab[(uint32_t)fS[t] & (64u * NCH - 1u)];
             }
 #pragma unroll
             for (int t = g0; t < g0 + G && t < SW; ++t) {
@@ -502,7 +518,8 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 
         // row j's ground and sky costs (ground is INF above vtop: bG is),
         // recorded for the backtracking
-        const float bS = ps_n, bG = pg_n;
+        const float bS = BLK ? readlane_f(blk.ps, jl) : ps_n;
+        const float bG = BLK ? ((j <= vtop) ? readlane_f(blk.pg, jl) : INF) : pg_n;
         const float Cg = bG + RG, Cs = bS + RS;
         if (wave == 0 && lane == 0) {
             L.crow_g[j] = Cg;
@@ -510,10 +527,12 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         }
 #pragma unroll
         for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
-        const int thi = thi_n, tlo = tlo_n;                   // bounds at base row b
+        // bounds at base row b
+        const int thi = BLK ? readlane_i(blk.thi, jl) : thi_n;
+        const int tlo = BLK ? readlane_i(blk.tlo, jl) : tlo_n;
         // pixel q_{j+1}, base b+1 (b <= H-1); tall columns read the pixel
-        // from LDS (a register held across their runtime loop spills)
-        load_next(b, (S <= 8) ? readlane_i(qblk, jl) : (int)in.q[b]);
+        // from LDS (registers held across their runtime loop spill)
+        load_next(b, BLK ? readlane_i(blk.q, jl) : (int)in.q[b]);
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
@@ -571,23 +590,27 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         for (int sj = 0; sj < S; ++sj) {
             const int jend = min(64, H - 1 - sj * 64);
             if (jend <= 0) break;
-            const int qblk = q_block(sj);
+            const Blk blk = load_block(sj);
             // steps whose base b = sj*64+jl+1 can still follow a ground stixel
             const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
-            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, qblk);
-            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, qblk);
+            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, blk);
+            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, blk);
         }
     } else {
         // tall columns: one runtime loop keeps the code (and the registers
         // live across it) to a single copy of the step
+        const Blk none;
         for (int j = 0; j < H - 1; ++j) {
-            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63, 0);
-            else step(std::false_type{}, j >> 6, j & 63, 0);
+            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63, none);
+            else step(std::false_type{}, j >> 6, j & 63, none);
         }
     }
 
     // the top row's ground and sky costs, and every row's object cost and
-    // mean, into LDS for the backtracking
+    // mean, into LDS for the backtracking.  Callers may keep the column's
+    // pixels (in.q) in the crow_o array until here: with several waves, no
+    // wave overwrites it before all have left the recurrence
+    if constexpr (W > 1) __syncthreads();
     if (wave == 0 && lane == 0) {
         L.crow_g[H - 1] = ((H - 1 <= vtop) ? buf_load(pgr, H) : INF) + RG;
         L.crow_s[H - 1] = buf_load(psr, H) + RS;

@@ -233,8 +233,10 @@ __device__ void copy_to_lds(float* lds, const float* g, int n) {
 // so that the recurrence gathers from LDS instead of the caches and HBM.
 template <int S, int NCH, int W, bool POL>
 __global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
-    __shared__ int16_t qs[64 * S];
-    __shared__ ColumnLds<S, W> lds;
+    __shared__ ColumnLds<S, W, 64 * NCH> lds;
+    // the column's reduced pixels live in the object row-cost array, which
+    // solve_column writes only after its last read of them
+    int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
     const int col = blockIdx.x;
     const int stride = a.H + 1;
     for (int v = threadIdx.x; v < a.H; v += 64 * W) qs[v] = a.q[(size_t)col * a.H + v];
