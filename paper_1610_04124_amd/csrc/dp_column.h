@@ -273,8 +273,11 @@ __device__ void backtrack_column(const int H, const int vtop, const Prior P, con
 // (d_range <= 64 NCH); W: waves per column (the workgroup is 64 W lanes, all
 // of which call this function).  POL: the recurrence gathers the object
 // prefix table from po_lds, an LDS copy of in.PO (the backtracking still
-// reads in.PO).  On return the results are written.
-template <int S, int NCH, int W, bool POL = false>
+// reads in.PO).  BLOCKS: short columns read their steps' wave-uniform
+// values a slot at a time (right for many waves per SIMD, which hide the
+// load at each slot boundary; a column alone on its SIMD keeps the per-step
+// prefetch).  On return the results are written.
+template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                              const ColumnOut& out, ColumnLds<S, W, 64 * NCH>& L,
                              const float* po_lds = nullptr) {
@@ -360,13 +363,15 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     uint32_t roff[NCH];
 #pragma unroll
     for (int c = 0; c < NCH; ++c) roff[c] = row_off(c);
-    // Short columns (S <= 8) read the wave-uniform values of the 64 steps
+    // Short columns (S <= 8) read wave-uniform values of the 64 steps
     // j = 64 sj + lane of a slot once, a lane per step: the pixel q_{j+1}
-    // the step prefetches, the sky and ground prefixes at j+1 and the
-    // bounds of the base row j+1 (top-down row H-2-j).  A step takes its own
-    // with readlane (scalar registers), so per step only the object
-    // gathers and the object-cost row are vector memory instructions.
-    constexpr bool BLK = (S <= 8);
+    // the step prefetches and, with BLOCKS, the sky and ground prefixes at
+    // j+1 and the bounds of the base row j+1 (top-down row H-2-j; without
+    // BLOCKS these four are prefetched a step ahead).  A step takes its own
+    // with readlane (scalar registers); with BLOCKS only the object gathers
+    // and the object-cost row are vector memory instructions of a step.
+    constexpr bool QB = (S <= 8);                    // the pixel a slot at a time
+    constexpr bool BLK = BLOCKS && QB;               // and the other four
     struct Blk {
         int q = 0, thi = 0, tlo = 0;
         float ps = 0.0f, pg = 0.0f;
@@ -375,10 +380,12 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         Blk k;
         const int j = 64 * sj + lane;
         k.q = (j + 1 < H) ? (int)in.q[j + 1] : -1;
-        k.ps = buf_load(psr, j + 1);                  // past the table: 0, never used
-        k.pg = buf_load(pgr, j + 1);
-        k.thi = __builtin_bit_cast(int, buf_load(fgh, H - 2 - j));
-        k.tlo = __builtin_bit_cast(int, buf_load(fgl, H - 2 - j));
+        if constexpr (BLK) {
+            k.ps = buf_load(psr, j + 1);              // past the table: 0, never used
+            k.pg = buf_load(pgr, j + 1);
+            k.thi = __builtin_bit_cast(int, buf_load(fgh, H - 2 - j));
+            k.tlo = __builtin_bit_cast(int, buf_load(fgl, H - 2 - j));
+        }
         return k;
     };
     auto load_next = [&](int v, int qv) {
@@ -532,7 +539,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         const int tlo = BLK ? readlane_i(blk.tlo, jl) : tlo_n;
         // pixel q_{j+1}, base b+1 (b <= H-1); tall columns read the pixel
         // from LDS (registers held across their runtime loop spill)
-        load_next(b, BLK ? readlane_i(blk.q, jl) : (int)in.q[b]);
+        load_next(b, QB ? readlane_i(blk.q, jl) : (int)in.q[b]);
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;

@@ -265,11 +265,11 @@ __global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
         const int n = (in.fmax - in.fbase + 1) * stride;   // uniform over the workgroup
         if (n <= a.lds_floats) {
             copy_to_lds<W>(po_lds, in.PO, n);
-            solve_column<S, NCH, W, true>(a.H, a.vtop, a.prior, in, out, lds, po_lds);
+            solve_column<S, NCH, W, true, false>(a.H, a.vtop, a.prior, in, out, lds, po_lds);
             return;
         }
     }
-    solve_column<S, NCH, W, false>(a.H, a.vtop, a.prior, in, out, lds);
+    solve_column<S, NCH, W, false, false>(a.H, a.vtop, a.prior, in, out, lds);
 }
 
 // ------------------------------------------------------------------ self-test
