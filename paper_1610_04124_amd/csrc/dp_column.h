@@ -28,6 +28,15 @@
 
 namespace stx {
 
+// f(std::integral_constant<int, I>) for I = B .. E-1, in order.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 struct ColumnIn {
     const float* PG;        // [H+1] ground cost prefix
     const float* PS;        // [H+1] sky cost prefix
@@ -434,7 +443,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // issued before any candidate is folded.  Steps where no ground stixel
     // can end at or below b-1 (b > vtop+1) skip the ground terms.  Slots
     // below the current row are skipped by uniform branches.
-    auto step = [&](auto gr_tag, const int sj, const int jl, const Blk& blk) {
+    // tj = sj / W, the owning wave's local slot of row j: a compile-time
+    // constant at every call, so that row j's registers are read by one
+    // readlane each (a run-time slot would read every slot and select)
+    auto step = [&](auto gr_tag, const int sj, const int jl, const int tj, const Blk& blk) {
         constexpr bool GR = decltype(gr_tag)::value;
         const int j = sj * 64 + jl, b = j + 1;
         // row j's object cost, mean and prefix values, read from its owning
@@ -445,7 +457,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         auto read_row = [&]() {
 #pragma unroll
             for (int t = 0; t < SW; ++t) {
-                if (t == sj / W) {
+                if (t == tj) {
                     Co = readlane_f(mO[t], jl);
                     fp = readlane_i(fO[t], jl);
                     bA = readlane_f(eA[t], jl);
@@ -600,16 +612,32 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             const Blk blk = load_block(sj);
             // steps whose base b = sj*64+jl+1 can still follow a ground stixel
             const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
-            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, blk);
-            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, blk);
+            for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, sj / W, blk);
+            for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, sj / W, blk);
         }
+    } else if constexpr (SW <= 8) {
+        // tall columns shared by several waves: one copy of the step per
+        // local slot of row j's owner (at most 8, as for short columns),
+        // the owning wave a run-time loop
+        const Blk none;
+        static_for<0, SW>([&](auto tc) {
+            constexpr int T = decltype(tc)::value;
+            for (int wj = 0; wj < W; ++wj) {
+                const int sj = T * W + wj;
+                const int jend = min(64, H - 1 - sj * 64);
+                if (jend <= 0) break;
+                const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
+                for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, T, none);
+                for (int jl = jgr; jl < jend; ++jl) step(std::false_type{}, sj, jl, T, none);
+            }
+        });
     } else {
-        // tall columns: one runtime loop keeps the code (and the registers
-        // live across it) to a single copy of the step
+        // tall one-wave columns: one runtime loop keeps the code (and the
+        // registers live across it) to a single copy of the step
         const Blk none;
         for (int j = 0; j < H - 1; ++j) {
-            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63, none);
-            else step(std::false_type{}, j >> 6, j & 63, none);
+            if (j + 1 <= vtop + 1) step(std::true_type{}, j >> 6, j & 63, (j >> 6) / W, none);
+            else step(std::false_type{}, j >> 6, j & 63, (j >> 6) / W, none);
         }
     }
 
