@@ -494,6 +494,9 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // inside the column's table or read 0 past its end, and their table
         // index is masked): skipping them one by one would cost more than
         // the work.  Groups bound the registers a tall column holds.
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
+
         constexpr int G = (SW <= 8) ? SW : 4;
         constexpr bool EARLY = (NCH == 2) && (S <= 8);
         float pk[SW];
@@ -532,6 +535,12 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             return g0 * W < nslots && (g0 + G - 1) * W + wave >= sj;
         };
         if constexpr (EARLY) {
+            // Only the previous step's object-cost row is still in flight
+            // here (issued a step ago).  Waiting for it now, explicitly,
+            // keeps the compiler from placing that wait after the gathers
+            // below, where the in-order memory counter would make it wait
+            // for the gathers too (vmcnt(0), expcnt and lgkmcnt untouched).
+            __builtin_amdgcn_s_waitcnt(0x0F70);
             if (group_open(0)) gather(0);
         }
 
@@ -544,8 +553,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             L.crow_g[j] = Cg;
             L.crow_s[j] = Cs;
         }
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
         // bounds at base row b
         const int thi = BLK ? readlane_i(blk.thi, jl) : thi_n;
         const int tlo = BLK ? readlane_i(blk.tlo, jl) : tlo_n;
@@ -610,6 +617,11 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             const int jend = min(64, H - 1 - sj * 64);
             if (jend <= 0) break;
             const Blk blk = load_block(sj);
+            // the slot's values are in registers before its steps start;
+            // otherwise the compiler's wait counts inside the step, which
+            // cannot tell the loop's iterations apart, would also wait for
+            // most of the step's own gathers before reading them
+            __builtin_amdgcn_s_waitcnt(0);
             // steps whose base b = sj*64+jl+1 can still follow a ground stixel
             const int jgr = min(jend, max(0, vtop + 1 - sj * 64));
             for (int jl = 0; jl < jgr; ++jl) step(std::true_type{}, sj, jl, sj / W, blk);
