@@ -91,7 +91,7 @@ def _time(run, stream, replays):
 WAVES = (1, 2, 4)
 
 
-def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAULT_CACHE,
+def tune(batch, items, stream, replays: int = 9, cache_path: str | None = DEFAULT_CACHE,
          force: bool = False, waves=WAVES) -> dict:
     """Pick and apply waves per column and the workgroup count for `items`
     on `batch`; returns the record (also cached).  Leaves the batch captured
@@ -124,10 +124,12 @@ def tune(batch, items, stream, replays: int = 5, cache_path: str | None = DEFAUL
             batch.capture(items, stream)
             timings[(c, w, g)] = _time(lambda: batch.replay(stream), stream, replays)
             ntasks[(c, w, g)] = nt
-    # near-ties (within 1 %) go to one column per wave, fewer waves per
-    # column, then fewer workgroups: the same speed for less of the device
+    # near-ties (within 0.25 %, about the replay-to-replay noise) go to one
+    # column per wave, fewer waves per column, then fewer workgroups: the
+    # same speed for less of the device.  (A 1 % margin picked grids that
+    # the kernel trace then showed 2-3 % slower.)
     fastest = min(timings.values())
-    best = min((k for k, v in timings.items() if v <= fastest * 1.01), key=lambda k: k)
+    best = min((k for k, v in timings.items() if v <= fastest * 1.0025), key=lambda k: k)
     batch.set_columns(best[0])
     batch.set_waves(best[1])
     batch.set_workgroups(best[2])
