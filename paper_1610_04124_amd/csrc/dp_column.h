@@ -484,6 +484,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             bA = bc[2];
             bN = bc[3];
         }
+        // the b-side object prefix column moves to PO[.][j+1]
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];
+
         // With two disparity chunks and up to eight slots, the gathers of
         // every open slot are issued first (they depend on row j's prefix
         // values only, not on its costs), so that their latency overlaps the
@@ -494,9 +498,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // inside the column's table or read 0 past its end, and their table
         // index is masked): skipping them one by one would cost more than
         // the work.  Groups bound the registers a tall column holds.
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) pcol[c] += orow[c];    // PO[.][j+1]
-
         constexpr int G = (SW <= 8) ? SW : 4;
         constexpr bool EARLY = (NCH == 2) && (S <= 8);
         float pk[SW];
