@@ -5,13 +5,22 @@ benchmark's CPU-baseline leg, never by the HIP library or its binding.
 
 Parity status of the oracle's functions (how each one is pinned to something
 other than itself is stated by the tests that do it):
-  pixel_cost     closed forms and the normalisation integral of Eq. 3
-  reduce         numpy sort / fsum on random strips
-  tables         rebuilt from pixel_cost + rounding, monotonicity, symmetry
-  column/frame   brute-force MAP over every segmentation of 1..10-row columns
-                 (ordering prior off: exact equality; on: the recurrence's own
-                 path cost, and never below the MAP), hand-solved special cases,
-                 invariants and synthetic-scene recovery.
+  pixel_cost     closed forms of Eq. 4, the Eq. 3 mixture bound, the sigma and
+                 quadratic terms isolated by differences
+  quantize       grid membership and the half-step error bound
+  tables         every table entry against Eq. 4 written with scipy's normal
+                 distribution (with the ground and object sigmas spelled out),
+                 monotonicity, the argmin of each row, the integer thresholds
+  reduce         numpy sort (lower median) and fsum (mean) on random strips
+  column/frame   prefix sums against direct sums; exhaustive search over every
+                 segmentation of 1..12-row columns (ordering prior off: exact
+                 cost and the first optimum in the tie order; on: the
+                 recurrence's own list cost, never below the MAP); a naive
+                 re-implementation of Eq. 5-6 with every prior term on, bit for
+                 bit on 240 random columns of up to 64 rows; hand-solved special
+                 cases and penalty boundaries; invariants and scene recovery.
+A mutation check (tests/test_oracle_mutants.py) plants 27 plausible mistakes
+in copies of the C source and requires each to fail one of these pins.
 Parity unpinned: agreement with the paper's authors' outputs and with the
 prior constants of Pfeiffer's thesis (neither is available).
 """

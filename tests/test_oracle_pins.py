@@ -140,6 +140,8 @@ def test_reduce_median_vs_numpy(s):
     disp[(bad > 0.2) & (bad < 0.22)] = np.inf
     disp[:, :s][:5] = -1                    # fully invalid strips
     disp[7] = np.round(disp[7]) + 0.5       # exact .5 ties -> half to even
+    disp[9] = 0.0                           # zero disparity is valid (sky)
+    disp[10, ::2] = -0.0                    # and so is negative zero
     p = synth.make_params(stixel_width=s, max_disparity=128)
     q = oracle.reduce(p, disp)
     ncols = W // s
@@ -432,14 +434,20 @@ def test_ordering_tolerance_boundary(tol, penalised):
     assert res["stixels"][1]["cost"] == expect
 
 
-@pytest.mark.parametrize("obj_disp,penalty", [(5, "gravity_cost"), (14, None), (30, "diving_cost")])
-def test_gravity_and_diving_penalties(obj_disp, penalty):
+@pytest.mark.parametrize("obj_disp,penalty,dive_tol", [
+    (5, "gravity_cost", 2.0), (14, None, 2.0), (30, "diving_cost", 2.0), (12, "gravity_cost", 2.0),
+    (13, None, 2.0), (17, "diving_cost", 2.0), (20, None, 6.0), (21, "diving_cost", 6.0)])
+def test_gravity_and_diving_penalties(obj_disp, penalty, dive_tol):
     """An object standing on the ground at base row 200, where the ground
     disparity is 0.25 * (259 - 200) = 14.75: far behind it (5 < 13) pays the
     gravity cost, in front of it (30 > 16) the diving cost, at it nothing.
+    The thresholds are ceil(14.75 - 2) = 13 and floor(14.75 + 2) = 16, both
+    strict: 12 and 17 pay, 13 does not; with a diving tolerance of 6 px the
+    upper one is 20 (an object at 16 would absorb the ground rows below
+    its base), so 20 does not pay and 21 does.
     The penalties are lowered so that the direct ground-to-object transition
     stays optimal and the penalty shows in the object's cost."""
-    m = dict(synth.DEFAULT_MODEL, gravity_cost=1.0, diving_cost=1.5)
+    m = dict(synth.DEFAULT_MODEL, gravity_cost=1.0, diving_cost=1.5, diving_tol_px=dive_tol)
     p = synth.make_params(model=m)
     H, vhor = 440, 259
     q = np.array([int(np.rint(0.25 * (vhor - v))) for v in range(200)]
