@@ -3,25 +3,34 @@
 One step = the whole hot path (column reduction, prefix tables, the
 three-class recurrence and backtracking) over one batch of 64 synthetic
 1024x440 frames (seeds 0..63), inputs resident in HBM.  The timed path is the
-persistent batched launch replayed from a HIP graph; the plain per-frame path
-(three kernels per frame, frames back to back on one stream) and per-frame /
-per-batch latency percentiles are reported beside it.
+persistent batched launch replayed from a HIP graph.  Beside it: the plain
+per-frame path (three staged kernels, and one fused launch) with per-frame
+latency percentiles and the HBM fraction of its reduction and table kernels;
+the 2048x880 batches; the 256-frame uneven batch; serving of 8 camera streams
+for 60 s; the CPU oracle on the host cores.
 
 Prints one JSON line.  Roofline of the dominant kernel (the persistent
 kernel): algorithmic work = 13 VALU lane-ops per (cut, row) pair of the
-recurrence, h(h+1)/2 pairs per column, against the plain VALU issue peak of
-256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz = 39.32 T lane-ops/s (the recurrence
-is min-plus, not a contraction, so MFMA peaks do not apply).
+recurrence (ground, sky and object candidate: prefix differences, the
+object mean, adds and minima), h(h+1)/2 pairs per column, against the plain
+VALU issue peak of 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-ops/s (the
+recurrence is min-plus, not a contraction, so MFMA peaks do not apply).  The
+fraction by the 7 lane-ops the object candidate alone needs (the ground and
+sky minima are separable) is reported beside it.
+
+    python bench.py [--steps K] [--warmup W]          the JSON line
+    python bench.py --profile-mode MODE [--launches N] one workload for rocprofv3
 """
 
 from __future__ import annotations
 
 import argparse
-import hashlib
 import glob
+import hashlib
 import json
 import os
 import statistics
+import subprocess
 import sys
 import time
 
@@ -30,13 +39,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "stixel frames/s @1024×440 w=5 (batched vs per-frame); p50/p99 frame latency"
 W, H, S_WIDTH, D_RANGE, FRAMES = 1024, 440, 5, 128, 64
-VALU_PEAK = 256 * 4 * 16 * 2.4e9          # lane-ops/s
-# Essential lane-ops per (cut, row) pair of the recurrence: the object
-# candidate's mean (two prefix differences, reciprocal-multiply, round),
-# its data term (one prefix difference), the prior add and the min.  The
-# ground and sky minima are separable (a running minimum per column step),
-# so they add O(h) per column, not work per pair.
-OPS_PER_PAIR = 7
+VALU_PEAK = 256 * 64 * 2.4e9              # lane-ops/s
+HBM_PEAK = 8.0e12                         # bytes/s
+OPS_PER_PAIR = 13                         # algorithmic lane-ops per (cut, row) pair
+OPS_SEPARABLE = 7                         # the object candidate's share alone
 
 
 def pairs_per_frame(W=W, H=H, s=S_WIDTH):
@@ -77,19 +83,95 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(frames, params, n_frames):
-    import oracle
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    sample = frames[:n_frames]
-    oracle.frame(params, sample[0], nthreads=threads)            # load / warm
+def r4(x):
+    return None if x is None else round(float(x), 4)
+
+
+def shader_clock_mhz():
+    """Current shader clock from rocm-smi (run before this process touches
+    the GPU), or None."""
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                             timeout=20).stdout
+    except Exception:
+        return None
+    for line in out.splitlines():
+        if "sclk" in line and "Mhz" in line:
+            tok = line.split("(")[-1].split("Mhz")[0]
+            try:
+                return float(tok)
+            except ValueError:
+                continue
+    return None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+# ------------------------------------------------------------------ workloads
+
+def headline_frames():
+    import synth
+    return [synth.generate_frame(synth.SceneSpec(seed=i)) for i in range(FRAMES)]
+
+
+def uneven_items(dev, flags=0):
+    """The 256 frames of the uneven workload (sizes 640x240 .. 2048x880,
+    stixel widths 3/5/7, own camera per size) with one handle per (size,
+    stixel width) and outputs; returns items and total (cut, row) pairs."""
+    import torch
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    handles, items, pairs = {}, [], 0
+    for i in range(256):
+        disp, info = synth.workload_frame("uneven256", i)
+        Wf, Hf, s = info["width"], info["height"], info["stixel_width"]
+        key = (Wf, Hf, s)
+        if key not in handles:
+            p = synth.make_params(camera=info["camera"], stixel_width=s,
+                                  max_disparity=info["d_max"], max_width=Wf, max_height=Hf,
+                                  flags=flags)
+            handles[key] = P.Stixels(p)
+        h = handles[key]
+        items.append((h, torch.from_numpy(disp).to(dev), h.new_output(Wf, Hf)))
+        pairs += (Wf // s) * Hf * (Hf + 1) // 2
+    return items, pairs
+
+
+def time_replays(batch, stream, warmup, steps):
+    """Graph replays timed with HIP events on the launch stream; returns
+    (wall seconds, per-replay milliseconds)."""
+    import torch
+    for _ in range(warmup):
+        batch.replay(stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     t0 = time.perf_counter()
-    for f in sample:
-        oracle.frame(params, f, nthreads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": round(len(sample) / dt, 3), "unit": "frames/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{len(sample)} of the {FRAMES} frames (seeds 0..{len(sample) - 1}), "
-                      f"C FP64 oracle, OpenMP over columns, {dt:.2f} s wall"}
+    for i in range(steps):
+        starts[i].record(stream)
+        batch.replay(stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+
+def tuned_capture(batch, items, stream, tune_launch):
+    if tune_launch:
+        from paper_1610_04124_amd.autotune import tune
+        return tune(batch, items, stream, cache_path=None)
+    batch.capture(items, stream)
+    return None
 
 
 def hires(warmup, steps, tune_launch=True):
@@ -109,34 +191,26 @@ def hires(warmup, steps, tune_launch=True):
     stream = torch.cuda.Stream()
     for s in (3, 5):
         params = synth.make_params(camera=cam, stixel_width=s, max_disparity=256, max_width=Wh,
-                                   max_height=Hh)
+                                   max_height=Hh, flags=P.binding.FLAG_BATCH_ONLY)
         h = P.Stixels(params)
         outs = [h.new_output(Wh, Hh) for _ in frames]
         b = P.Batch(16, 16 * (Wh // s), Hh, 256)
         torch.cuda.synchronize()
-        items = list(zip([h] * 16, frames, outs))
-        if tune_launch:
-            from paper_1610_04124_amd.autotune import tune
-            tuned = tune(b, items, stream, cache_path=None)
-        else:
-            b.capture(items, stream)
-        for _ in range(warmup):
-            b.replay(stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            b.replay(stream)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        tuned_capture(b, list(zip([h] * 16, frames, outs)), stream, tune_launch)
+        wall, ms = time_replays(b, stream, warmup, steps)
+        dt = wall / steps
+        avg = statistics.mean(ms) * 1e-3
         pairs = 16 * (Wh // s) * Hh * (Hh + 1) // 2
         g, _ = b.info()
         out[f"s{s}"] = {"fps": round(16 / dt, 2), "ms_per_batch": round(dt * 1e3, 4),
-                        "valu_frac": round(OPS_PER_PAIR * pairs / dt / VALU_PEAK, 4),
-                        "waves_per_column": b.waves(), "workgroups": g}
+                        "valu_frac": round(OPS_PER_PAIR * pairs / avg / VALU_PEAK, 4),
+                        "valu_frac_7op": round(OPS_SEPARABLE * pairs / avg / VALU_PEAK, 4),
+                        "waves_per_column": b.waves(), "columns_per_wave": b.columns(),
+                        "workgroups": g}
     return out
 
 
-def mean_mode(warmup, steps, tune_launch=True):
+def mean_mode(d_frames, warmup, steps, tune_launch=True):
     """The batched headline workload with the paper's own reduction (the
     mean of each strip's valid pixels, Sec. 4.1) instead of the median."""
     import torch
@@ -144,39 +218,124 @@ def mean_mode(warmup, steps, tune_launch=True):
     import synth
     import paper_1610_04124_amd as P
 
-    dev = torch.device("cuda", 0)
-    params = synth.make_params(reduce_mode=1)
+    params = synth.make_params(reduce_mode=1, flags=P.binding.FLAG_BATCH_ONLY)
     h = P.Stixels(params)
-    frames = [torch.from_numpy(synth.generate_frame(synth.SceneSpec(seed=i))).to(dev)
-              for i in range(FRAMES)]
-    outs = [h.new_output(W, H) for _ in frames]
+    outs = [h.new_output(W, H) for _ in d_frames]
     stream = torch.cuda.Stream()
     b = P.Batch(FRAMES, FRAMES * (W // S_WIDTH), H, D_RANGE)
-    items = list(zip([h] * FRAMES, frames, outs))
     torch.cuda.synchronize()
-    if tune_launch:
-        from paper_1610_04124_amd.autotune import tune
-        tune(b, items, stream, cache_path=None)
-    else:
-        b.capture(items, stream)
-    for _ in range(warmup):
-        b.replay(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        b.replay(stream)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+    tuned_capture(b, list(zip([h] * FRAMES, d_frames, outs)), stream, tune_launch)
+    wall, _ = time_replays(b, stream, warmup, steps)
+    dt = wall / steps
     g, _ = b.info()
     return {"fps": round(FRAMES / dt, 2), "ms_per_batch": round(dt * 1e3, 4),
             "waves_per_column": b.waves(), "workgroups": g,
             "reduction": "mean of the strip's valid pixels (reduce_mode 1)"}
 
 
-def serve(seconds, rate_scale=1.0):
+def uneven(warmup, steps, tune_launch=True):
+    """The 256-frame uneven batch in one autotuned persistent launch."""
+    import torch
+
+    import paper_1610_04124_amd as P
+
+    dev = torch.device("cuda", 0)
+    items, pairs = uneven_items(dev, flags=P.binding.FLAG_BATCH_ONLY)
+    ntasks = sum(h.num_columns(d.shape[1]) for h, d, _ in items)
+    b = P.Batch(256, ntasks, 880, 256)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    tuned = tuned_capture(b, items, stream, tune_launch)
+    wall, ms = time_replays(b, stream, warmup, steps)
+    avg = statistics.mean(ms) * 1e-3
+    g, t = b.info()
+    res = {"fps": round(256 * steps / wall, 2), "ms_per_batch": round(wall * 1e3 / steps, 4),
+           "batch_latency_ms_p50": r4(percentile(ms, 0.5)),
+           "batch_latency_ms_p99": r4(percentile(ms, 0.99)),
+           "valu_frac": round(OPS_PER_PAIR * pairs / avg / VALU_PEAK, 4),
+           "frames": 256, "tasks": t, "workgroups": g, "waves_per_column": b.waves(),
+           "columns_per_wave": b.columns(),
+           "sizes": "640x240, 1024x440, 1280x720, 2048x880; stixel widths 3/5/7; one launch"}
+    if tuned is not None:
+        res["autotune_tried_ms"] = tuned["tried"]
+    return res
+
+
+def per_frame_legs(h, d_frames, outs, stream, steps, latency_frames, tune_launch):
+    """The per-frame paths: three staged kernels and one fused launch.  Per
+    path: throughput with frames back to back, and latency per frame (HIP
+    events around each call, a synchronisation between frames).  For the
+    staged path also the time of each kernel and the HBM fraction of the
+    reduction and table kernels."""
+    import torch
+
+    from paper_1610_04124_amd import binding as B
+
+    res = {}
+    frame_tuned = None
+    if tune_launch:
+        from paper_1610_04124_amd.autotune import tune_frame
+        frame_tuned = tune_frame(h, d_frames[0], outs[0], stream)
+    for name, path in (("staged", 1), ("fused", 2)):
+        h.set_frame_path(path)
+        for i in range(len(d_frames)):
+            h.compute(d_frames[i], outs[i], stream)
+        torch.cuda.synchronize()
+        reps = max(1, steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for i in range(len(d_frames)):
+                h.compute(d_frames[i], outs[i], stream)
+        torch.cuda.synchronize()
+        fps = len(d_frames) * reps / (time.perf_counter() - t0)
+        lat = []
+        for i in range(latency_frames):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            h.compute(d_frames[i % len(d_frames)], outs[i % len(d_frames)], stream)
+            b.record(stream)
+            b.synchronize()
+            lat.append(a.elapsed_time(b))
+        res[name] = {"fps": round(fps, 2), "frame_latency_ms_p50": r4(percentile(lat, 0.5)),
+                     "frame_latency_ms_p99": r4(percentile(lat, 0.99))}
+    h.set_frame_path(0)
+    res["waves_per_column"] = h.waves(W, H)
+    if frame_tuned is not None:
+        res["po_placement"] = "lds" if frame_tuned["po_placement"] == 2 else "hbm"
+        res["autotune_tried_ms"] = frame_tuned["tried"]
+    # stage split: kernel times between HIP events, median over frames
+    times = [h.stage_times(d_frames[i % len(d_frames)], outs[i % len(d_frames)], stream)
+             for i in range(32)]
+    med = [statistics.median(t[k] for t in times) for k in range(3)]
+    rows = h.debug_stage(B.STAGE_RANGE, W, H, stream)
+    po_rows = int(sum(int(hi) - int(lo) + 1 for lo, hi in rows))
+    ncols = W // S_WIDTH
+    red_bytes = 4 * S_WIDTH * ncols * H + 2 * ncols * H
+    tab_bytes = 2 * ncols * H + 4 * 4 * ncols * (H + 1) + 4 * po_rows * (H + 1)
+    res["stages"] = {
+        "reduce_kernel": {"us": round(med[0] * 1e3, 2), "bytes": red_bytes,
+                          "hbm_frac": round(red_bytes / (med[0] * 1e-3) / HBM_PEAK, 4)},
+        "tables_kernel": {"us": round(med[1] * 1e3, 2), "bytes": tab_bytes,
+                          "object_prefix_rows": po_rows,
+                          "hbm_frac": round(tab_bytes / (med[1] * 1e-3) / HBM_PEAK, 4)},
+        "dp_kernel": {"us": round(med[2] * 1e3, 2),
+                      "valu_frac": round(OPS_PER_PAIR * pairs_per_frame() / (med[2] * 1e-3)
+                                         / VALU_PEAK, 4)},
+        "share": [round(x / sum(med), 4) for x in med],
+        "bytes_note": "reduction: strips read + reduced column written; tables: reduced "
+                      "column read + four small prefix tables + the object prefix rows of each "
+                      "column's own disparity range written (last frame's range)"}
+    return res
+
+
+def serve(seconds, rate_scale=1.0, budget_frames=None, pool=32):
     """8 cameras (1024x440, 1280x720, 2048x880 by camera index, stixel width
     5) at 30 Hz Poisson each (times rate_scale), served with continuous
-    batching in real time."""
+    batching in real time; every camera draws from `pool` distinct frames.
+    The HBM budget covers the resident tables and scratch plus the admitted
+    frames: 64 GiB, or with budget_frames the resident bytes plus that many
+    footprints of the largest camera's frame (so that admission binds)."""
     import torch
 
     import synth
@@ -185,47 +344,162 @@ def serve(seconds, rate_scale=1.0):
 
     dev = torch.device("cuda", 0)
     cams = serving_cameras(8)
-    per_cam = 4
     frames = {}
     for c, cam in enumerate(cams):
-        W, Hc, D = cam.width, cam.height, cam.handle.D
-        for i in range(per_cam):
-            spec = synth.SceneSpec(W, Hc, D, synth.camera_for_size(W, Hc), seed=1000 * c + i)
+        Wc, Hc, D = cam.width, cam.height, cam.handle.D
+        for i in range(pool):
+            spec = synth.SceneSpec(Wc, Hc, D, synth.camera_for_size(Wc, Hc), seed=1000 * c + i)
             frames[(c, i)] = torch.from_numpy(synth.generate_frame(spec)).to(dev)
     ex = GpuExecutor(cams, streams=3, max_frames=64)
-    waves = ex.tune({c: [frames[(c, i)] for i in range(per_cam)] for c in range(len(cams))})
-    srv = Server(cams, ex, hbm_budget=8 << 30, max_batch=64, keep_outputs=False)
-    arrivals = poisson_arrivals([30.0 * rate_scale] * 8, seconds, [42 + c for c in range(8)],
-                                per_cam)
+    layout = ex.tune({c: [frames[(c, i)] for i in range(8)] for c in range(len(cams))})
+    resident = ex.resident_bytes()
+    frame_bytes = sum(frames[(c, 0)].numel() * 4 for c in range(8)) * pool
+    budget = 64 << 30
+    if budget_frames:
+        budget = resident + budget_frames * max(c.footprint() for c in cams)
+    srv = Server(cams, ex, hbm_budget=budget, max_batch=64, keep_outputs=False,
+                 resident_bytes=resident)
+    arrivals = poisson_arrivals([30.0 * rate_scale] * 8, seconds, [42 + c for c in range(8)], pool)
     torch.cuda.synchronize()
     srv.run_trace(arrivals, lambda c, i: frames[(c, i)])
     torch.cuda.synchronize()
     st = srv.stats()
     st = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
-    st.update({"cameras": 8, "rate_hz_per_camera": 30 * rate_scale, "seconds": seconds,
-               "waves_per_column_by_slots": {str(k): v for k, v in sorted(waves.items())},
+    st.update({"arrivals": len(arrivals), "cameras": 8, "rate_hz_per_camera": 30 * rate_scale,
+               "seconds": seconds, "distinct_frames_per_camera": pool,
+               "frame_pool_bytes": frame_bytes,
+               "layout_by_height_class": {str(k): v for k, v in sorted(layout.items())},
                "sizes": "1024x440, 1280x720, 2048x880 by camera index; stixel width 5"})
     return st
 
+
+def cpu_baseline(frames, params, seconds_all=12.0, seconds_one=10.0):
+    """The FP64 oracle as it stands on the host cores: all cores (OpenMP over
+    columns), then one core, each on as many of the 64 frames as fit the
+    time given (a bounded sample)."""
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {}
+    for label, nt, budget in (("all", threads, seconds_all), ("one", 1, seconds_one)):
+        oracle.frame(params, frames[0], nthreads=nt)                # load / warm
+        n, t0 = 0, time.perf_counter()
+        while n < len(frames) and (n == 0 or time.perf_counter() - t0 < budget):
+            oracle.frame(params, frames[n], nthreads=nt)
+            n += 1
+        dt = time.perf_counter() - t0
+        out[label] = (n / dt, nt, n, dt)
+    fps, nt, n, dt = out["all"]
+    fps1, _, n1, dt1 = out["one"]
+    return {"value": round(fps, 3), "unit": "frames/s", "cores": nt, "kind": "oracle",
+            "sample": f"{n} of the {FRAMES} 1024x440 frames (seeds 0..{n - 1}), C FP64 oracle, "
+                      f"OpenMP over columns, {dt:.2f} s wall",
+            "one_core": {"value": round(fps1, 3), "unit": "frames/s", "cores": 1,
+                         "sample": f"{n1} frames, {dt1:.2f} s wall"},
+            "cpu_model": cpu_model()}
+
+
+# ------------------------------------------------------------------ profile modes
+
+def profile_mode(args):
+    """One workload, for rocprofv3 runs:
+    batch   the persistent batched launch over 64 frames 1024x440 (stixel
+            width 5), replayed from a HIP graph --launches times;
+    hires   the same over 16 frames of 2048x880 (stixel width 5, d_range 256);
+    uneven  the 256-frame uneven batch;
+    frame   the staged per-frame path (three kernels) on the 64 frames;
+    fused   the fused per-frame path (one launch per frame) on the 64 frames;
+    copy    a plain 256 MiB device-to-device copy, whose FETCH_SIZE and
+            WRITE_SIZE readings calibrate the HBM byte counters."""
+    import torch
+
+    dev = torch.device("cuda", 0)
+    if args.profile_mode == "copy":
+        n = 256 * 1024 * 1024 // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.launches):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copied {n * 4} bytes x {args.launches}", flush=True)
+        return
+
+    import synth
+    import paper_1610_04124_amd as P
+
+    stream = torch.cuda.Stream()
+    if args.profile_mode == "uneven":
+        items, _ = uneven_items(dev)
+        ntasks = sum(h.num_columns(d.shape[1]) for h, d, _ in items)
+        b = P.Batch(256, ntasks, 880, 256, args.workgroups)
+        b.set_waves(args.waves)
+        torch.cuda.synchronize()
+        b.capture(items, stream)
+        for _ in range(args.launches):
+            b.replay(stream)
+        torch.cuda.synchronize()
+        print(f"uneven: {args.launches} launches over 256 frames", flush=True)
+        return
+    if args.profile_mode == "hires":
+        Wp, Hp, D, nframes = 2048, 880, 256, 16
+        cam = synth.camera_for_size(Wp, Hp)
+        params = synth.make_params(camera=cam, max_width=Wp, max_height=Hp, max_disparity=D)
+        specs = [synth.SceneSpec(Wp, Hp, D, cam, seed=i) for i in range(nframes)]
+    else:
+        Wp, Hp, D, nframes = W, H, D_RANGE, FRAMES
+        params = synth.make_params()
+        specs = [synth.SceneSpec(seed=i) for i in range(nframes)]
+    h = P.Stixels(params)
+    h.set_waves(args.waves)
+    h.set_po_placement(args.placement)
+    frames = [torch.from_numpy(synth.generate_frame(sp)).to(dev) for sp in specs]
+    outs = [h.new_output(Wp, Hp) for _ in frames]
+    torch.cuda.synchronize()
+    if args.profile_mode in ("batch", "hires"):
+        b = P.Batch(len(frames), len(frames) * (Wp // 5), Hp, D, args.workgroups)
+        b.set_waves(args.waves)
+        b.capture(list(zip([h] * len(frames), frames, outs)), stream)
+        for _ in range(args.launches):
+            b.replay(stream)
+    else:
+        h.set_frame_path(1 if args.profile_mode == "frame" else 2)
+        for _ in range(args.launches):
+            for f, o in zip(frames, outs):
+                h.compute(f, o, stream)
+    torch.cuda.synchronize()
+    print(f"{args.profile_mode}: {args.launches} launches over {len(frames)} frames", flush=True)
+
+
+# ------------------------------------------------------------------ main
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-frames", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--latency-frames", type=int, default=200)
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--profile-mode", choices=["batch", "hires", "uneven", "frame", "fused", "copy"])
+    ap.add_argument("--launches", type=int, default=3)
+    ap.add_argument("--waves", type=int, default=0,
+                    help="profile modes: waves per column (0: automatic per frame, one batched)")
+    ap.add_argument("--workgroups", type=int, default=0,
+                    help="profile modes: resident workgroups of the batched launch (0: occupancy)")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="profile modes: object prefix table placement (0 auto, 1 HBM, 2 LDS)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(frames and columns are independent, see the design notes "
                                    "on sharding)"}))
         sys.exit(2)
+    if args.profile_mode:
+        profile_mode(args)
+        return
 
-    import numpy as np
+    sclk = shader_clock_mhz()             # before this process touches the GPU
+
     import torch
 
     import synth
@@ -233,78 +507,43 @@ def main():
 
     dev = torch.device("cuda", 0)
     params = synth.make_params()
-    frames = [synth.generate_frame(synth.SceneSpec(seed=i)) for i in range(FRAMES)]
+    frames = headline_frames()
     d_frames = [torch.from_numpy(f).to(dev) for f in frames]
     h = P.Stixels(params)
     outs = [h.new_output(W, H) for _ in range(FRAMES)]
     stream = torch.cuda.Stream()            # a created stream: graphs cannot capture the null stream
     torch.cuda.synchronize()
+    tune_launch = not args.no_tune
 
     # ---------------- batched path: persistent launch replayed from a graph
     batch = P.Batch(FRAMES, FRAMES * (W // S_WIDTH), H, D_RANGE)
     items = list(zip([h] * FRAMES, d_frames, outs))
-    tuned = None
-    if args.no_tune:
-        batch.capture(items, stream)
-    else:
-        from paper_1610_04124_amd.autotune import tune
-        tuned = tune(batch, items, stream, cache_path=None)
+    tuned = tuned_capture(batch, items, stream, tune_launch)
     grid, ntasks = batch.info()
     waves = batch.waves()
     columns = batch.columns()
-    for _ in range(args.warmup):
-        batch.replay(stream)
-    torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(stream)
-        batch.replay(stream)
-        ends[i].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    wall, launch_ms = time_replays(batch, stream, args.warmup, args.steps)
     batched_fps = FRAMES * args.steps / wall
     ms_per_step = wall * 1e3 / args.steps
     avg_launch_s = statistics.mean(launch_ms) * 1e-3
 
-    # ---------------- per-frame path: three kernels per frame, one stream
-    frame_tuned = None
-    if not args.no_tune:
-        from paper_1610_04124_amd.autotune import tune_frame
-        frame_tuned = tune_frame(h, d_frames[0], outs[0], stream)
-    frame_waves = h.waves(W, H)
-    for i in range(FRAMES):
-        h.compute(d_frames[i], outs[i], stream)
-    torch.cuda.synchronize()
-    reps = max(1, args.steps // 5)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        for i in range(FRAMES):
-            h.compute(d_frames[i], outs[i], stream)
-    torch.cuda.synchronize()
-    per_frame_fps = FRAMES * reps / (time.perf_counter() - t0)
-    lat = []
-    for i in range(args.latency_frames):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        h.compute(d_frames[i % FRAMES], outs[i % FRAMES], stream)
-        b.record(stream)
-        b.synchronize()
-        lat.append(a.elapsed_time(b))
-
     # ---------------- roofline of the persistent kernel
-    ops = OPS_PER_PAIR * pairs_per_frame() * FRAMES
+    pairs = pairs_per_frame() * FRAMES
+    ops = OPS_PER_PAIR * pairs
     achieved = ops / avg_launch_s
     kernel = f"batch_kernel<7, 2, {waves}>" if columns == 1 else "batch_pair_kernel<7, 2>"
     traffic = traffic_from_profiles(kernel, grid)
-    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(VALU_PEAK / 1e12, 4),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
-                "kernel": kernel, "ops_per_launch": ops,
-                "avg_launch_ms": round(avg_launch_s * 1e3, 4)}
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4),
+                "peak": round(VALU_PEAK / 1e12, 4), "unit": "TOP/s",
+                "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
+                "kernel": kernel, "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs,
+                "ops_per_launch": ops, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+                "frac_7op": round(OPS_SEPARABLE * pairs / avg_launch_s / VALU_PEAK, 4),
+                "sclk_mhz_at_start": sclk}
+
+    # ---------------- per-frame paths
+    per_frame = per_frame_legs(h, d_frames, outs, stream, args.steps, args.latency_frames,
+                               tune_launch)
 
     result = {
         "metric": METRIC, "value": round(batched_fps, 2), "unit": "frames/s", "n_gpus": 1,
@@ -318,29 +557,32 @@ def main():
                    "workgroups": grid, "tasks": ntasks, "waves_per_column": waves,
                    "columns_per_wave": columns},
         "batched": {"fps": round(batched_fps, 2),
-                    "batch_latency_ms_p50": round(percentile(launch_ms, 0.5), 4),
-                    "batch_latency_ms_p99": round(percentile(launch_ms, 0.99), 4)},
-        "per_frame": {"fps": round(per_frame_fps, 2), "waves_per_column": frame_waves,
-                      "po_placement": (None if frame_tuned is None else
-                                       ("lds" if frame_tuned["po_placement"] == 2 else "hbm")),
-                      "frame_latency_ms_p50": round(percentile(lat, 0.5), 4),
-                      "frame_latency_ms_p99": round(percentile(lat, 0.99), 4)},
+                    "batch_latency_ms_p50": r4(percentile(launch_ms, 0.5)),
+                    "batch_latency_ms_p99": r4(percentile(launch_ms, 0.99))},
+        "per_frame": per_frame,
         "roofline": roofline,
         "paper_context_fps": {"titan_x": 413, "tegra_x1": 26, "i7_980x_cpu": 13.3},
     }
     if tuned is not None:
         result["config"]["autotune_tried_ms"] = tuned["tried"]
-    if frame_tuned is not None:
-        result["per_frame"]["autotune_tried_ms"] = frame_tuned["tried"]
-    result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5), not args.no_tune)
-    result["batched_mean_reduction"] = mean_mode(args.warmup, max(3, args.steps // 5),
-                                                  not args.no_tune)
+    print("[bench] batched and per-frame legs done", file=sys.stderr, flush=True)
+    result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5), tune_launch)
+    result["batched_mean_reduction"] = mean_mode(d_frames, args.warmup, max(3, args.steps // 5),
+                                                 tune_launch)
+    result["uneven256"] = uneven(args.warmup, max(3, args.steps // 5), tune_launch)
+    print("[bench] hires, mean and uneven legs done", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         result["serving"] = serve(args.serve_seconds)
+        print("[bench] serving at 30 Hz done", file=sys.stderr, flush=True)
         # the same cameras at 16x the rate: continuous batching under load
-        result["serving_loaded"] = serve(args.serve_seconds / 2, rate_scale=16.0)
+        loaded_s = min(10.0, args.serve_seconds)
+        result["serving_loaded"] = serve(loaded_s, rate_scale=16.0)
+        # and with an HBM budget that binds: the resident bytes plus room for
+        # 8 frames of the largest camera
+        result["serving_admission_bound"] = serve(loaded_s, rate_scale=16.0, budget_frames=8)
+        print("[bench] serving legs done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(frames, params, args.cpu_frames)
+        result["cpu_baseline"] = cpu_baseline(frames, params)
     print(json.dumps(result), flush=True)
 
 

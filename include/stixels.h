@@ -84,8 +84,13 @@ typedef struct {
     int32_t max_stixels_per_column; /* output records per column, 0 = the frame height */
     int32_t reduce_mode;         /* 0 = lower median of the valid pixels, 1 = mean (Sec. 4.1) */
     int32_t cost_grid_log2;      /* g: costs are multiples of 2^-g nats, 0..12 */
-    int32_t reserved0;
+    int32_t flags;               /* STIXELS_FLAG_* bits, 0 = none */
 } stixels_params;
+
+/* stixels_params.flags: the handle is used only through the batch API
+ * (stixels_batch_*, stixels_compute_batch), so stixels_create allocates no
+ * per-frame workspace and stixels_compute returns STIXELS_E_INVALID_ARG. */
+#define STIXELS_FLAG_BATCH_ONLY 1
 
 /* One stixel, 12 bytes.  v_bottom..v_top are inclusive bottom-up rows;
  * disparity is the rounded mean of an object's valid pixels, 0 otherwise;
@@ -126,11 +131,24 @@ int stixels_create(const stixels_params *params, stixels_handle **out);
 /* Release the tables and the workspace.  NULL is accepted. */
 int stixels_destroy(stixels_handle *h);
 
+/* Device bytes the handle holds: its resident tables, its per-frame
+ * workspace (none with STIXELS_FLAG_BATCH_ONLY) and the batch object of
+ * stixels_compute_batch, if one exists. */
+int stixels_device_bytes(const stixels_handle *h, size_t *bytes);
+
 /* Number of reduced columns of a frame of this width: floor(width / s). */
 int stixels_num_columns(const stixels_handle *h, int32_t width, int32_t *ncols);
 
 /* Records per column that an output for a frame of this height must hold. */
 int stixels_output_capacity(const stixels_handle *h, int32_t height, int32_t *capacity);
+
+/* Device bytes of the four output arrays of a frame of this size (Sec. 4.4:
+ * a fixed-capacity list per column): ncols * (4 counts + capacity * 12
+ * records + 4 total + 1 overflow), ncols = floor(width / s) and capacity as
+ * stixels_output_capacity.  The caller allocates them (one buffer or four)
+ * and fills a stixels_output.  STIXELS_E_INVALID_ARG for a null handle or
+ * pointer, width < s or height < 1. */
+int stixels_output_bytes(const stixels_handle *h, int32_t width, int32_t height, size_t *bytes);
 
 /* Segment one frame (Sec. 4.1-4.4): column reduction and transpose, the
  * per-column prefix-sum tables, the Eq. 5-6 recurrence and backtracking.
@@ -141,6 +159,21 @@ int stixels_output_capacity(const stixels_handle *h, int32_t height, int32_t *ca
  * or the batch API).  Allocates nothing. */
 int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, int32_t height,
                     void *stream, const stixels_output *out);
+
+/* How stixels_compute runs a frame: 1 = three staged kernels (reduction and
+ * transpose, prefix tables into the handle's workspace, recurrence and
+ * backtracking: Sec. 4.1, 4.2, 4.3-4.4 as separate steps, as in the paper);
+ * 2 = one launch of the persistent fused kernel of the batch API over the
+ * frame's columns (each column reduced, tabulated, solved and backtracked
+ * inside one workgroup, its tables in a scratch slot of the handle's
+ * workspace); 0 (the default) = automatic (currently 1).  Results do not
+ * depend on it.  The intermediates of stixels_debug_stage exist only after a
+ * staged call.  STIXELS_E_INVALID_ARG for other values. */
+int stixels_set_frame_path(stixels_handle *h, int32_t path);
+
+/* The path (1 or 2) stixels_compute takes under the current setting (0 for a
+ * null handle). */
+int stixels_get_frame_path(const stixels_handle *h);
 
 /* Wavefronts per column of the recurrence in stixels_compute (Sec. 4.3
  * assigns one thread block per column; here a column's rows are shared by
@@ -229,6 +262,17 @@ int stixels_batch_set_waves(stixels_batch *b, int32_t waves);
 /* Waves per column of the last compute or capture (0 before the first). */
 int stixels_batch_waves(const stixels_batch *b);
 
+/* One-call form of the batch API: segment n frames (any cameras, sizes and
+ * stixel widths) in one persistent launch on `stream`, as
+ * stixels_batch_compute, through a batch object owned by the first job's
+ * handle.  That object is created on the first call and grown (after a
+ * device synchronisation) when a call needs more jobs, columns, rows or
+ * disparities than every earlier one; other calls allocate nothing.  Calls
+ * whose first job names the same handle must not overlap, like
+ * stixels_compute on that handle.  Errors are reported on the first job's
+ * handle (stixels_last_error). */
+int stixels_compute_batch(const stixels_job *jobs, int32_t n, void *stream);
+
 /* Columns per wave64 of later calls: 1, or 2 (two columns of one frame
  * share a wave, one per 32-lane half, so that the recurrence's per-step work
  * serves both), which applies where h <= 512 and d_range <= 128 and with
@@ -238,6 +282,10 @@ int stixels_batch_set_columns(stixels_batch *b, int32_t columns);
 
 /* Columns per wave of the last compute or capture (0 before the first). */
 int stixels_batch_columns(const stixels_batch *b);
+
+/* Device bytes the batch object holds (descriptors, task lists and the
+ * per-workgroup scratch slots). */
+int stixels_batch_device_bytes(const stixels_batch *b, size_t *bytes);
 
 /* Workgroups of the persistent launch last used, and the number of
  * tasks (frame columns) of the last call. */
@@ -256,13 +304,19 @@ enum { STIXELS_TABLE_SKY = 0, STIXELS_TABLE_GROUND = 1, STIXELS_TABLE_OBJECT = 2
        STIXELS_TABLE_FG_HI = 3, STIXELS_TABLE_FG_LO = 4 };
 int stixels_debug_table(const stixels_handle *h, int32_t which, void *host_dst, size_t bytes);
 
+/* All five tables above in one host buffer, in the order SKY, GROUND,
+ * OBJECT, FG_HI, FG_LO, each laid out as for stixels_debug_table; bytes must
+ * equal the sum of their sizes. */
+int stixels_debug_tables(const stixels_handle *h, void *host_dst, size_t bytes);
+
 /* The same tables built on the host from `params` alone, without a handle or
  * a device (validation and range checks as in stixels_create; the error
  * text is then available from stixels_last_error(NULL)). */
 int stixels_host_table(const stixels_params *params, int32_t which, void *host_dst, size_t bytes);
 
 /* Host copies of the intermediates of the last stixels_compute on this
- * handle (synchronises `stream` first).  With ncols columns of height h:
+ * handle, which must have taken the staged path (synchronises `stream`
+ * first).  With ncols columns of height h:
  *   REDUCED  int16[ncols][h]               reduced bottom-up disparities, -1 invalid
  *   PREFIX   float[4][ncols][h+1]          ground, sky, 2*sum(q)+count, 2*count prefixes
  *   RANGE    int32[ncols][2]               smallest / largest valid q of each column
@@ -272,6 +326,15 @@ enum { STIXELS_STAGE_REDUCED = 0, STIXELS_STAGE_PREFIX = 1, STIXELS_STAGE_RANGE 
        STIXELS_STAGE_OBJECT_PREFIX = 3 };
 int stixels_debug_stage(const stixels_handle *h, int32_t which, void *host_dst, size_t bytes,
                         void *stream);
+
+/* One frame through the staged path of stixels_compute with HIP events on
+ * `stream` between its three kernels; synchronises and writes the
+ * milliseconds of the reduction (Sec. 4.1), the prefix tables (Sec. 4.2) and
+ * the recurrence with backtracking (Sec. 4.3-4.4) to host_ms[0..2].  For
+ * measurements; the results equal those of stixels_compute. */
+int stixels_debug_stage_times(stixels_handle *h, const float *d_disparity, int32_t width,
+                              int32_t height, void *stream, const stixels_output *out,
+                              float *host_ms);
 
 /* Exhaustive device check of the rounded object mean used by the recurrence:
  * for every count n in 1..max_height and every sum S in 0..n*(d_range-1),

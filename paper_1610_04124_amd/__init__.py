@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     FrameOutput,
     Stixels,
     StixelsError,
+    compute_batch,
     decode_records,
     host_table,
     lib,
@@ -18,5 +19,5 @@ from .binding import (  # noqa: F401
     status_string,
 )
 
-__all__ = ["Batch", "Stixels", "FrameOutput", "StixelsError", "decode_records", "host_table", "lib", "selftest_mean",
-           "status_string", "EXPORTS"]
+__all__ = ["Batch", "Stixels", "FrameOutput", "StixelsError", "compute_batch", "decode_records",
+           "host_table", "lib", "selftest_mean", "status_string", "EXPORTS"]

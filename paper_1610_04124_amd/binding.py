@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstixels.so")
 
 OK, E_INVALID_ARG, E_RANGE, E_HIP, E_NOMEM = 0, -1, -2, -3, -4
+FLAG_BATCH_ONLY = 1
 TABLE_SKY, TABLE_GROUND, TABLE_OBJECT, TABLE_FG_HI, TABLE_FG_LO = range(5)
 STAGE_REDUCED, STAGE_PREFIX, STAGE_RANGE, STAGE_OBJECT_PREFIX = range(4)
 
@@ -31,7 +32,10 @@ EXPORTS = (
     "stixels_batch_set_columns", "stixels_batch_columns",
     "stixels_set_waves", "stixels_get_waves", "stixels_set_po_placement",
     "stixels_batch_last_error", "stixels_debug_table", "stixels_host_table",
-    "stixels_debug_stage", "stixels_selftest_mean",
+    "stixels_debug_stage", "stixels_selftest_mean", "stixels_output_bytes",
+    "stixels_compute_batch", "stixels_debug_tables", "stixels_set_frame_path",
+    "stixels_get_frame_path", "stixels_device_bytes", "stixels_batch_device_bytes",
+    "stixels_debug_stage_times",
 )
 
 
@@ -62,7 +66,7 @@ class Params(C.Structure):
                 ("max_disparity", C.c_int32), ("max_width", C.c_int32),
                 ("max_height", C.c_int32), ("max_stixels_per_column", C.c_int32),
                 ("reduce_mode", C.c_int32), ("cost_grid_log2", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class Output(C.Structure):
@@ -124,6 +128,15 @@ def lib():
         L.stixels_set_waves.argtypes = [vp, i32]
         L.stixels_get_waves.argtypes = [vp, i32, i32]
         L.stixels_set_po_placement.argtypes = [vp, i32]
+        L.stixels_output_bytes.argtypes = [vp, i32, i32, P(C.c_size_t)]
+        L.stixels_compute_batch.argtypes = [P(Job), i32, vp]
+        L.stixels_debug_tables.argtypes = [vp, vp, C.c_size_t]
+        L.stixels_set_frame_path.argtypes = [vp, i32]
+        L.stixels_get_frame_path.argtypes = [vp]
+        L.stixels_device_bytes.argtypes = [vp, P(C.c_size_t)]
+        L.stixels_batch_device_bytes.argtypes = [vp, P(C.c_size_t)]
+        L.stixels_debug_stage_times.argtypes = [vp, vp, i32, i32, vp, P(Output),
+                                                P(C.c_float)]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
         _lib = L
@@ -147,6 +160,7 @@ def to_params(params: dict) -> Params:
     for k in ("stixel_width", "max_disparity", "max_width", "max_height",
               "max_stixels_per_column", "reduce_mode", "cost_grid_log2"):
         setattr(p, k, int(params[k]))
+    p.flags = int(params.get("flags", 0))
     return p
 
 
@@ -268,6 +282,32 @@ class Stixels:
         """Wavefronts per column that compute uses for a frame of this size."""
         return int(lib().stixels_get_waves(self.h, int(height), int(width)))
 
+    def set_frame_path(self, path: int) -> None:
+        """How compute runs a frame: 1 staged kernels, 2 one fused launch, 0 automatic."""
+        rc = lib().stixels_set_frame_path(self.h, int(path))
+        if rc != OK:
+            self._err(rc, "stixels_set_frame_path")
+
+    def frame_path(self) -> int:
+        """The path (1 staged, 2 fused) compute takes under the current setting."""
+        return int(lib().stixels_get_frame_path(self.h))
+
+    def device_bytes(self) -> int:
+        """Device bytes the handle holds (tables, workspace, internal batch)."""
+        n = C.c_size_t()
+        rc = lib().stixels_device_bytes(self.h, C.byref(n))
+        if rc != OK:
+            self._err(rc, "stixels_device_bytes")
+        return n.value
+
+    def output_bytes(self, width: int, height: int) -> int:
+        """Device bytes of a frame's four output arrays."""
+        n = C.c_size_t()
+        rc = lib().stixels_output_bytes(self.h, int(width), int(height), C.byref(n))
+        if rc != OK:
+            self._err(rc, "stixels_output_bytes")
+        return n.value
+
     def new_output(self, width: int, height: int, device=None) -> FrameOutput:
         import torch
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
@@ -280,12 +320,25 @@ class Stixels:
         H, W = disp.shape
         if out is None:
             out = self.new_output(W, H, disp.device)
+        self.check_output(out, W, disp.device)
         o = out.struct()
         rc = lib().stixels_compute(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
                                    _stream_ptr(stream), C.byref(o))
         if rc != OK:
             self._err(rc, "stixels_compute")
         return out
+
+    def check_output(self, out: FrameOutput, width: int, device) -> None:
+        """The kernels write ncols columns of `capacity` records into the
+        output's tensors; a mismatched output would be overrun on the device."""
+        if out.ncols != self.num_columns(width):
+            raise ValueError(f"output holds {out.ncols} columns, the frame has "
+                             f"{self.num_columns(width)}")
+        if out.counts.device != device:
+            raise ValueError("output and input are on different devices")
+        if (out.records.shape != (out.ncols, out.capacity, 3) or out.counts.numel() != out.ncols
+                or out.total.numel() != out.ncols or out.overflow.numel() != out.ncols):
+            raise ValueError("output tensors do not match its column count and capacity")
 
     def compute_raw(self, disp_ptr: int, W: int, H: int, out: Output, stream_ptr) -> None:
         rc = lib().stixels_compute(self.h, C.c_void_p(disp_ptr), int(W), int(H), stream_ptr,
@@ -301,6 +354,35 @@ class Stixels:
         if rc != OK:
             self._err(rc, "stixels_debug_table")
         return a
+
+    def stage_times(self, disp, out: FrameOutput, stream=None):
+        """Milliseconds of the staged path's reduction, tables and recurrence
+        kernels for one frame (HIP events between them; synchronises)."""
+        import torch
+        _check_device_tensor(disp, torch.float32, "disparity")
+        H, W = disp.shape
+        self.check_output(out, W, disp.device)
+        o = out.struct()
+        ms = (C.c_float * 3)()
+        rc = lib().stixels_debug_stage_times(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
+                                             _stream_ptr(stream), C.byref(o), ms)
+        if rc != OK:
+            self._err(rc, "stixels_debug_stage_times")
+        return [float(x) for x in ms]
+
+    def debug_tables(self) -> dict:
+        """All offline tables in one call (stixels_debug_tables)."""
+        shapes = [_table_shape(w, self.D, self.max_height) for w in range(5)]
+        sizes = [int(np.prod(sh)) * np.dtype(dt).itemsize for sh, dt in shapes]
+        buf = np.zeros(sum(sizes), np.uint8)
+        rc = lib().stixels_debug_tables(self.h, buf.ctypes.data, buf.nbytes)
+        if rc != OK:
+            self._err(rc, "stixels_debug_tables")
+        out, off = {}, 0
+        for w, (sh, dt), n in zip(range(5), shapes, sizes):
+            out[w] = buf[off:off + n].view(dt).reshape(sh).copy()
+            off += n
+        return out
 
     def debug_stage(self, which: int, W: int, H: int, stream=None) -> np.ndarray:
         ncols = W // self.s
@@ -349,6 +431,17 @@ def finite(x):
     return x if math.isfinite(x) else math.inf
 
 
+def compute_batch(items, stream=None):
+    """One-call batch (stixels_compute_batch): items as for Batch.compute; the
+    batch object lives in the first item's handle."""
+    arr, keep = Batch.make_jobs(items)
+    rc = lib().stixels_compute_batch(arr, len(arr), _stream_ptr(stream))
+    if rc != OK:
+        raise StixelsError(rc, "stixels_compute_batch: " +
+                           lib().stixels_last_error(items[0][0].h).decode())
+    return keep
+
+
 class Batch:
     """Persistent batched launch over many frames (possibly different cameras,
     sizes and stixel widths); see stixels_batch_* in include/stixels.h."""
@@ -390,6 +483,7 @@ class Batch:
         for i, (h, disp, out) in enumerate(items):
             _check_device_tensor(disp, torch.float32, "disparity")
             H, W = disp.shape
+            h.check_output(out, W, disp.device)
             arr[i].handle = h.h
             arr[i].d_disparity = disp.data_ptr()
             arr[i].width, arr[i].height = int(W), int(H)
@@ -440,6 +534,14 @@ class Batch:
         rc = lib().stixels_batch_set_workgroups(self.b, int(n))
         if rc != OK:
             self._err(rc, "stixels_batch_set_workgroups")
+
+    def device_bytes(self) -> int:
+        """Device bytes the batch object holds."""
+        n = C.c_size_t()
+        rc = lib().stixels_batch_device_bytes(self.b, C.byref(n))
+        if rc != OK:
+            self._err(rc, "stixels_batch_device_bytes")
+        return n.value
 
     def info(self):
         g, t = C.c_int32(), C.c_int32()

@@ -27,7 +27,14 @@ FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(_HERE, "csrc", "*.hip")))
+    """Every HIP unit, the per-slot-count kernel units with the most rows
+    (the slowest to compile) first."""
+    def key(path):
+        name = os.path.basename(path)
+        if name.startswith("inst_s"):
+            return (0, -int(name[len("inst_s"):-len(".hip")]))
+        return (1, name)
+    return sorted(glob.glob(os.path.join(_HERE, "csrc", "*.hip")), key=key)
 
 
 def build(verbose: bool = False) -> str:

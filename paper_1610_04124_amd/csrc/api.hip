@@ -1,6 +1,7 @@
 // api.hip -- C ABI of the stixel library: handle creation (offline tables of
 // Sec. 3.4 built in FP64 on the host, rounded to the cost grid, made resident
 // in HBM), the per-frame compute entry point and the debug exports.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -9,6 +10,7 @@
 #include <vector>
 
 #include "handle.h"
+#include "job_desc.h"
 #include "launch.h"
 #include "stixels.h"
 
@@ -81,6 +83,7 @@ int validate(const stixels_params* p, std::string& why) {
     if (p->max_stixels_per_column < 0) return bad("max_stixels_per_column must be >= 0");
     if (p->reduce_mode != 0 && p->reduce_mode != 1) return bad("reduce_mode must be 0 or 1");
     if (p->cost_grid_log2 < 0 || p->cost_grid_log2 > 12) return bad("cost_grid_log2 must lie in 0..12");
+    if (p->flags & ~STIXELS_FLAG_BATCH_ONLY) return bad("unknown bits in flags");
     if ((long long)p->max_height * p->max_disparity > (1LL << 20)) {
         why = "max_height * max_disparity must not exceed 2^20 (rounded-mean division bound)";
         return STIXELS_E_RANGE;
@@ -188,6 +191,9 @@ int build_tables(stixels_handle* h) {
 
 thread_local std::string g_create_error;
 
+// Path of stixels_compute: the request, or automatically the staged kernels.
+int frame_path_of(const stixels_handle* h) { return h->frame_path == 0 ? 1 : h->frame_path; }
+
 }  // namespace
 
 extern "C" {
@@ -226,12 +232,17 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     if (rc == STIXELS_OK) rc = upload(h, &h->d_object_df, h->object_df);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_hi, h->fg_hi);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_lo, h->fg_lo);
-    if (rc == STIXELS_OK) {
+    if (rc == STIXELS_OK && !(params->flags & STIXELS_FLAG_BATCH_ONLY)) {
         const size_t nc = (size_t)h->ncols_max, H1 = (size_t)h->Hmax + 1;
+        // d_po holds the staged path's object prefix tables or, for the
+        // fused path, its descriptor, task list and one scratch slot per
+        // column
+        h->ws_bytes = std::max(nc * h->D * H1 * sizeof(float) + kTableGuardBytes,
+                               persist::frame_fused_bytes(h->ncols_max, h->Hmax, h->D, h->ncols_max));
         bool ok = hipMalloc(reinterpret_cast<void**>(&h->d_q), nc * h->Hmax * sizeof(int16_t)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_prefix), 4 * nc * H1 * sizeof(float)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_range), 2 * nc * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(reinterpret_cast<void**>(&h->d_po), nc * h->D * H1 * sizeof(float) + kTableGuardBytes) == hipSuccess;
+                  hipMalloc(reinterpret_cast<void**>(&h->d_po), h->ws_bytes) == hipSuccess;
         if (!ok) rc = fail(h, STIXELS_E_NOMEM, "hipMalloc of the frame workspace failed");
     }
     if (rc != STIXELS_OK) {
@@ -246,8 +257,24 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
 
 int stixels_destroy(stixels_handle* h) {
     if (!h) return STIXELS_OK;
+    stixels_batch_destroy(h->auto_batch);
     release(h);
     delete h;
+    return STIXELS_OK;
+}
+
+int stixels_device_bytes(const stixels_handle* h, size_t* bytes) {
+    if (!h || !bytes) return STIXELS_E_INVALID_ARG;
+    size_t n = (h->sky.size() + h->ground.size() + h->object_t.size() + h->object_df.size() +
+                h->fg_hi.size() + h->fg_lo.size()) * 4;
+    if (h->d_po) {
+        const size_t nc = (size_t)h->ncols_max, H1 = (size_t)h->Hmax + 1;
+        n += nc * h->Hmax * sizeof(int16_t) + 4 * nc * H1 * sizeof(float) +
+             2 * nc * sizeof(int32_t) + h->ws_bytes;
+    }
+    size_t b = 0;
+    if (h->auto_batch && stixels_batch_device_bytes(h->auto_batch, &b) == STIXELS_OK) n += b;
+    *bytes = n;
     return STIXELS_OK;
 }
 
@@ -274,7 +301,22 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
     if (height < 1 || height > h->Hmax)
         return fail(h, STIXELS_E_INVALID_ARG, "height outside [1, max_height]");
     if (out->capacity < 1) return fail(h, STIXELS_E_INVALID_ARG, "output capacity must be >= 1");
+    if (!h->d_po)
+        return fail(h, STIXELS_E_INVALID_ARG, "handle created for the batch API only (no workspace)");
     const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int waves = frame_waves(h->waves, height, width / h->s, h->num_cu);
+    if (frame_path_of(h) == 2) {
+        int grid = 0;
+        const hipError_t e = persist::launch_frame_fused(
+            persist::make_job_desc(h, d_disparity, width, height, *out), h->d_po, h->ws_bytes,
+            waves, h->num_cu, st, &grid);
+        if (e != hipSuccess)
+            return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+        h->last_W = width;
+        h->last_H = height;
+        h->last_path = 2;
+        return STIXELS_OK;
+    }
     const int ncols = width / h->s;
     const int vtop = ground_top(h->p.camera.horizon_row, height);
     DeviceModel m = device_model(h);
@@ -283,7 +325,6 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
                    out->overflow, out->capacity};
     hipError_t e = launch_reduce(m, d_disparity, width, height, ncols, ws.q, st);
     if (e == hipSuccess) e = launch_tables(m, ws, height, ncols, vtop, st);
-    const int waves = frame_waves(h->waves, height, ncols, h->num_cu);
     if (e == hipSuccess)
         e = launch_dp(m, ws, height, ncols, vtop, waves, frame_po_lds(h->po_placement, height),
                       h->lds_per_block, fo, st);
@@ -291,6 +332,67 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
         return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
     h->last_W = width;
     h->last_H = height;
+    h->last_path = 1;
+    return STIXELS_OK;
+}
+
+int stixels_debug_stage_times(stixels_handle* h, const float* d_disparity, int32_t width,
+                              int32_t height, void* stream, const stixels_output* out,
+                              float* host_ms) {
+    if (!h || !host_ms) return STIXELS_E_INVALID_ARG;
+    if (!d_disparity || !out || !out->counts || !out->records || !out->total_cost ||
+        !out->overflow || out->capacity < 1 || width < h->s || width > h->Wmax || height < 1 ||
+        height > h->Hmax || !h->d_po)
+        return fail(h, STIXELS_E_INVALID_ARG, "invalid frame, output or batch-only handle");
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const int ncols = width / h->s;
+    const int vtop = ground_top(h->p.camera.horizon_row, height);
+    const int waves = frame_waves(h->waves, height, ncols, h->num_cu);
+    DeviceModel m = device_model(h);
+    FrameWorkspace ws{h->d_q, h->d_prefix, h->d_range, h->d_po};
+    FrameOutput fo{out->counts, reinterpret_cast<uint32_t*>(out->records), out->total_cost,
+                   out->overflow, out->capacity};
+    hipEvent_t ev[4] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = launch_reduce(m, d_disparity, width, height, ncols, ws.q, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = launch_tables(m, ws, height, ncols, vtop, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess)
+        e = launch_dp(m, ws, height, ncols, vtop, waves, frame_po_lds(h->po_placement, height),
+                      h->lds_per_block, fo, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventElapsedTime(&host_ms[i], ev[i], ev[i + 1]);
+    for (int i = 0; i < 4; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess)
+        return fail(h, STIXELS_E_HIP, std::string("timed staged frame failed: ") + hipGetErrorString(e));
+    h->last_W = width;
+    h->last_H = height;
+    h->last_path = 1;
+    return STIXELS_OK;
+}
+
+int stixels_set_frame_path(stixels_handle* h, int32_t path) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (path < 0 || path > 2)
+        return fail(h, STIXELS_E_INVALID_ARG, "frame path must be 0 (auto), 1 (staged) or 2 (fused)");
+    h->frame_path = path;
+    return STIXELS_OK;
+}
+
+int stixels_get_frame_path(const stixels_handle* h) { return h ? frame_path_of(h) : 0; }
+
+int stixels_output_bytes(const stixels_handle* h, int32_t width, int32_t height, size_t* bytes) {
+    int32_t ncols = 0, cap = 0;
+    if (!bytes || stixels_num_columns(h, width, &ncols) != STIXELS_OK ||
+        stixels_output_capacity(h, height, &cap) != STIXELS_OK)
+        return STIXELS_E_INVALID_ARG;
+    *bytes = (size_t)ncols * (sizeof(int32_t) + (size_t)cap * sizeof(stixels_record) +
+                              sizeof(float) + sizeof(uint8_t));
     return STIXELS_OK;
 }
 
@@ -354,6 +456,22 @@ int stixels_debug_table(const stixels_handle* h, int32_t which, void* host_dst, 
     return copy_table(h, which, host_dst, bytes);
 }
 
+int stixels_debug_tables(const stixels_handle* h, void* host_dst, size_t bytes) {
+    if (!h || !host_dst) return STIXELS_E_INVALID_ARG;
+    const size_t parts[5] = {h->sky.size() * 4, h->ground.size() * 4, h->object_t.size() * 4,
+                             h->fg_hi.size() * 4, h->fg_lo.size() * 4};
+    size_t total = 0;
+    for (size_t x : parts) total += x;
+    if (bytes != total) return STIXELS_E_INVALID_ARG;
+    char* dst = static_cast<char*>(host_dst);
+    for (int which = 0; which < 5; ++which) {
+        const int rc = copy_table(h, which, dst, parts[which]);
+        if (rc != STIXELS_OK) return rc;
+        dst += parts[which];
+    }
+    return STIXELS_OK;
+}
+
 int stixels_host_table(const stixels_params* params, int32_t which, void* host_dst,
                        size_t bytes) {
     if (!params || !host_dst) return STIXELS_E_INVALID_ARG;
@@ -380,6 +498,7 @@ int stixels_host_table(const stixels_params* params, int32_t which, void* host_d
 int stixels_debug_stage(const stixels_handle* h, int32_t which, void* host_dst, size_t bytes,
                         void* stream) {
     if (!h || !host_dst || h->last_H < 1) return STIXELS_E_INVALID_ARG;
+    if (h->last_path != 1) return STIXELS_E_INVALID_ARG;   // the fused path keeps no per-frame tables
     const size_t ncols = (size_t)(h->last_W / h->s), H = (size_t)h->last_H;
     const void* src = nullptr;
     size_t n = 0;

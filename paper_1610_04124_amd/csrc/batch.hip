@@ -1,513 +1,46 @@
-// batch.hip -- many frames in one persistent fused launch.
-//
-// Every (frame, column) pair is a task.  The host orders tasks by decreasing
-// frame height (the recurrence costs O(h^2) per column, Sec. 3.3), so the
-// longest columns start first, and resident single-wave workgroups pull
-// tasks from a device counter until the list is exhausted.  Each task runs
-// the whole per-column pipeline of Sec. 4 without leaving the workgroup:
-// strip reduction into LDS, the prefix tables and object prefix rows into
-// the workgroup's own scratch slot (written and re-read by the same wave,
-// so they stay in L2), then the recurrence and backtracking of dp_column.h.
-// Results are bit-identical to the per-frame kernels: the arithmetic is the
-// same exact grid arithmetic, only the schedule differs.
+// batch.hip -- many frames in one persistent fused launch: job validation,
+// the decreasing-height task list, descriptor staging, launches and HIP graph
+// capture.  The kernel itself is in batch_kernel.h.
 #include <algorithm>
 #include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
 
-#include "dp_column.h"
-#include "handle.h"
+#include "job_desc.h"
+#include "kernel_table.h"
 #include "launch.h"
 #include "stixels.h"
 
 using namespace stx;
 
-// A named namespace (not an anonymous one) so that profilers show the
-// kernels by name.
 namespace stx::persist {
 
-struct JobDesc {
-    const float* disp;
-    const float* sky;
-    const float* ground;
-    const float* object_t;
-    const float* object_df;
-    const int32_t* fg_hi;
-    const int32_t* fg_lo;
-    int32_t* counts;
-    uint32_t* records;
-    float* total;
-    uint8_t* overflow;
-    int W, H, s, ncols, D, vtop, reduce_mode, cap;
-    Prior prior;
-};
-
-__device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D) {
-    switch (s) {
-#define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D);
-        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
-        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
-        STX_CASE(14) STX_CASE(15) STX_CASE(16)
-#undef STX_CASE
-        default: return -1;
-    }
-}
-
-__device__ __forceinline__ int wave_min_i(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
-    return x;
-}
-__device__ __forceinline__ int wave_max_i(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
-    return x;
-}
-
+// Resets the task counter before a launch (a kernel node, not a memset, so
+// that a captured graph replays it correctly).
 __global__ void reset_counter_kernel(unsigned int* c) { *c = 0u; }
-
-// Start delay between consecutive XCDs of a long batched launch, in shader
-// clock cycles (~5 us).
-constexpr unsigned int kXcdStaggerCycles = 10000u;
-
-// Waves per SIMD the register allocation of each variant is held to (the
-// compiler's own choice leaves a few registers above the next step down;
-// multi-wave workgroups keep a little more room for the row broadcast).
-constexpr int batch_waves(int slots_per_wave, int waves) {
-    return slots_per_wave <= 7 ? (waves == 1 ? 5 : 4) : (slots_per_wave <= 14 ? 3 : 2);
-}
-
-// One workgroup of W waves per column task.
-template <int S, int NCH, int W>
-__global__ __launch_bounds__(64 * W)
-__attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch_kernel(
-    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
-    unsigned int* counter, float* scratch, long long scratch_stride, int hmax,
-    unsigned int stagger) {
-    __shared__ ColumnLds<S, W, 64 * NCH> lds;
-    // the column's reduced pixels live in the object row-cost array, which
-    // solve_column writes only after its last read of them
-    int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
-    __shared__ int task_slot;
-    __shared__ int red[3][W];
-    const int lane = threadIdx.x & 63;
-    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
-    (void)hmax;
-    // Workgroups are dispatched to the eight XCDs in turn.  When every
-    // column takes equally long, all of them would reach the memory-heavy
-    // table builds together, round after round; starting XCD x stagger * x
-    // cycles late spreads those bursts over the shared memory system
-    // (measured: 2 % at 1024x440, insensitive to the delay's size).
-    if (stagger != 0u) {
-        const unsigned int xcd = blockIdx.x & 7u;
-        const unsigned long long t0 = __builtin_amdgcn_s_memtime();
-        const unsigned long long dl = (unsigned long long)xcd * stagger;
-        while (__builtin_amdgcn_s_memtime() - t0 < dl) __builtin_amdgcn_s_sleep(127);
-    }
-    for (;;) {
-        int t = 0;
-        if constexpr (W == 1) {
-            if (lane == 0) t = (int)atomicAdd(counter, 1u);
-            t = __builtin_amdgcn_readfirstlane(t);
-        } else {
-            if (threadIdx.x == 0) task_slot = (int)atomicAdd(counter, 1u);
-            __syncthreads();
-            t = __builtin_amdgcn_readfirstlane(task_slot);
-        }
-        if (t >= ntasks) break;
-        const int2 tk = tasks[t];
-        const JobDesc& J = jobs[tk.x];
-        const int H = J.H, D = J.D, col = tk.y, stride = H + 1;
-
-        // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
-        int lmin = INT_MAX, lmax = -1;
-        bool inv = false;
-        for (int v = threadIdx.x; v < H; v += 64 * W) {
-            const int r = H - 1 - v;
-            const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
-                                     J.reduce_mode, D);
-            qs[v] = (int16_t)x;
-            if (x >= 0) {
-                lmin = min(lmin, x);
-                lmax = max(lmax, x);
-            } else {
-                inv = true;
-            }
-        }
-        // object means lie in [smallest, largest valid q]; a stixel without
-        // valid pixels has mean 0, so the table starts at 0 when the column
-        // holds an invalid pixel
-        int anyinv = __ballot(inv) ? 1 : 0;
-        int fmin = wave_min_i(lmin);
-        int fmax = wave_max_i(lmax);
-        if constexpr (W > 1) {
-            if (lane == 0) {
-                red[0][wave] = fmin;
-                red[1][wave] = fmax;
-                red[2][wave] = anyinv;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                fmin = min(fmin, red[0][w]);
-                fmax = max(fmax, red[1][w]);
-                anyinv |= red[2][w];
-            }
-        }
-        if (anyinv) fmin = 0;
-        if (fmax < 0) {
-            fmin = 0;
-            fmax = 0;
-        }
-        // the same in every lane; reading them from the first lane lets the
-        // compiler keep them (and the row offsets derived from them) scalar
-        fmin = __builtin_amdgcn_readfirstlane(fmin);
-        fmax = __builtin_amdgcn_readfirstlane(fmax);
-        __syncthreads();
-
-        // Sec. 4.2: prefix tables into the scratch slot: the four small ones
-        // by wave 0, the object rows f = fmin + wave, fmin + wave + W, ...
-        // Every load of a table row (one per 64-row slot) is issued before
-        // its scan starts, so a row costs one memory latency rather than one
-        // per slot.
-        float* PG = ws;
-        float* PS = ws + stride;
-        float* PA = ws + 2 * stride;
-        float* PN = ws + 3 * stride;
-        float* PO = ws + 4 * stride;
-        const int nsl = (H + 63) >> 6;
-        auto q_at = [&](int c) {
-            const int v = 64 * c + lane;
-            return (v < H) ? (int)qs[v] : -1;
-        };
-        if (wave == 0) {
-            if (lane == 0) {
-                PG[0] = 0.0f;
-                PS[0] = 0.0f;
-                PA[0] = 0.0f;
-                PN[0] = 0.0f;
-            }
-            float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
-            for (int c = 0; c < nsl; ++c) {
-                const int v = 64 * c + lane, x = q_at(c);
-                float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
-                if (x >= 0) {
-                    g = J.ground[(size_t)(H - 1 - v) * D + x];
-                    sk = J.sky[x];
-                    aa = (float)(2 * x + 1);
-                    nn = 2.0f;
-                }
-                g = wave_inclusive_scan(g) + cg;
-                sk = wave_inclusive_scan(sk) + cs;
-                aa = wave_inclusive_scan(aa) + ca;
-                nn = wave_inclusive_scan(nn) + cn;
-                if (v < H) {
-                    PG[v + 1] = g;
-                    PS[v + 1] = sk;
-                    PA[v + 1] = aa;
-                    PN[v + 1] = nn;
-                }
-                cg = readlane_f(g, 63);
-                cs = readlane_f(sk, 63);
-                ca = readlane_f(aa, 63);
-                cn = readlane_f(nn, 63);
-            }
-        }
-        const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
-        // the column's object rows, stored through one buffer resource with a
-        // per-lane offset and the row's offset in a scalar register
-        const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
-        // Byte offset of each slot's pixel within an object-cost row (2^30
-        // for an invalid pixel or a row past H: in the per-lane offset, which
-        // the bounds check always covers, so such lanes read 0); a row's
-        // offset is then the scalar part of every load.
-        uint32_t qoff[S];
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const int x = q_at(c);
-            qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
-        }
-        // With several waves per column the loads of row f + W are in flight
-        // while row f is scanned; one-wave workgroups have no registers to
-        // spare for it (measured: double buffering made them spill and run
-        // slower) and load each row just before scanning it.
-        constexpr bool DB = (W > 1);
-        float oc[S], on[S];
-        auto load_row = [&](float (&o)[S], int f) {
-            const uint32_t rowb = (uint32_t)(f * D) * 4u;
-#pragma unroll
-            for (int c = 0; c < S; ++c) o[c] = buf_load_b(otr, qoff[c], rowb);
-        };
-        if constexpr (DB) {
-            if (fmin + wave <= fmax) load_row(oc, fmin + wave);
-        }
-#pragma unroll 1
-        for (int f = fmin + wave; f <= fmax; f += W) {
-            if constexpr (DB) {
-                if (f + W <= fmax) load_row(on, f + W);
-            } else {
-                load_row(oc, f);
-            }
-            const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
-            if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
-            // slots past H load zeros and store nothing: no per-slot branch,
-            // so the slots' scans can interleave
-            float carry = 0.0f;
-#pragma unroll
-            for (int c = 0; c < S; ++c) {
-                const int v = 64 * c + lane;
-                const float o = wave_inclusive_scan(oc[c]) + carry;
-                if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
-                carry = readlane_f(o, 63);
-            }
-            if constexpr (DB) {
-#pragma unroll
-                for (int c = 0; c < S; ++c) oc[c] = on[c];
-            }
-        }
-        __syncthreads();   // the tables written above are read back below, by every wave
-
-        // Sec. 4.3-4.4
-        ColumnIn in;
-        in.PG = PG;
-        in.PS = PS;
-        in.PA = PA;
-        in.PN2 = PN;
-        in.PO = PO;
-        in.fbase = fmin;
-        in.fmax = fmax;
-        in.q = qs;
-        in.O_df = J.object_df;
-        in.D = D;
-        in.fg_hi = J.fg_hi;
-        in.fg_lo = J.fg_lo;
-        ColumnOut out;
-        out.count = J.counts + col;
-        out.rec = J.records + (size_t)col * J.cap * 3;
-        out.total = J.total + col;
-        out.overflow = J.overflow + col;
-        out.cap = J.cap;
-        solve_column<S, NCH, W>(H, J.vtop, J.prior, in, out, lds);
-        __syncthreads();   // every read of the slot completes before the next task rewrites it
-    }
-}
-
-// Sec. 4.1-4.2 for one column by one wave: its strips reduced into qs (LDS,
-// bottom-up; -1 past H and for a column that does not exist), then its
-// prefix tables at ws (PG, PS, PA, PN at 0..3 (h+1), the object rows from
-// po_at floats on).  Returns the column's disparity range [fmin, fmax].
-template <int S>
-__device__ void column_tables(const JobDesc& J, const int col, const bool exists, int16_t* qs,
-                              float* ws, const int po_at, int& fmin_out, int& fmax_out) {
-    const int lane = threadIdx.x & 63;
-    const int H = J.H, D = J.D, stride = H + 1;
-    int lmin = INT_MAX, lmax = -1;
-    bool inv = false;
-    for (int v = lane; v < 64 * S; v += 64) {
-        int x = -1;
-        if (exists && v < H)
-            x = reduce_any(J.disp + (size_t)(H - 1 - v) * J.W + (size_t)col * J.s, J.s,
-                           J.reduce_mode, D);
-        qs[v] = (int16_t)x;
-        if (x >= 0) {
-            lmin = min(lmin, x);
-            lmax = max(lmax, x);
-        } else if (v < H) {
-            inv = true;
-        }
-    }
-    int fmin = __ballot(inv) ? 0 : wave_min_i(lmin);
-    int fmax = wave_max_i(lmax);
-    if (fmax < 0) {
-        fmin = 0;
-        fmax = 0;
-    }
-    fmin = __builtin_amdgcn_readfirstlane(fmin);
-    fmax = __builtin_amdgcn_readfirstlane(fmax);
-    fmin_out = fmin;
-    fmax_out = fmax;
-    __syncthreads();
-    float* PG = ws;
-    float* PS = ws + stride;
-    float* PA = ws + 2 * stride;
-    float* PN = ws + 3 * stride;
-    if (lane == 0) {
-        PG[0] = 0.0f;
-        PS[0] = 0.0f;
-        PA[0] = 0.0f;
-        PN[0] = 0.0f;
-    }
-    float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
-    for (int base = 0; base < H; base += 64) {
-        const int v = base + lane;
-        const int x = (v < H) ? (int)qs[v] : -1;
-        float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
-        if (x >= 0) {
-            g = J.ground[(size_t)(H - 1 - v) * D + x];
-            sk = J.sky[x];
-            aa = (float)(2 * x + 1);
-            nn = 2.0f;
-        }
-        g = wave_inclusive_scan(g) + cg;
-        sk = wave_inclusive_scan(sk) + cs;
-        aa = wave_inclusive_scan(aa) + ca;
-        nn = wave_inclusive_scan(nn) + cn;
-        if (v < H) {
-            PG[v + 1] = g;
-            PS[v + 1] = sk;
-            PA[v + 1] = aa;
-            PN[v + 1] = nn;
-        }
-        cg = readlane_f(g, 63);
-        cs = readlane_f(sk, 63);
-        ca = readlane_f(aa, 63);
-        cn = readlane_f(nn, 63);
-    }
-    const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
-    const auto pow_ =
-        make_rsrc(ws + po_at, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
-    uint32_t qoff[S];
-#pragma unroll
-    for (int c = 0; c < S; ++c) {
-        const int v = 64 * c + lane;
-        const int x = (v < H) ? (int)qs[v] : -1;
-        qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
-    }
-#pragma unroll 1
-    for (int f = fmin; f <= fmax; ++f) {
-        const uint32_t rowb = (uint32_t)(f * D) * 4u;
-        float oc[S];
-#pragma unroll
-        for (int c = 0; c < S; ++c) oc[c] = buf_load_b(otr, qoff[c], rowb);
-        const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
-        if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
-        float carry = 0.0f;
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const int v = 64 * c + lane;
-            const float o = wave_inclusive_scan(oc[c]) + carry;
-            if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
-            carry = readlane_f(o, 63);
-        }
-    }
-}
-
-// Two columns of one frame per one-wave workgroup (solve_pair): tasks are
-// (frame, even column) pairs.  The workgroup's scratch slot holds the two
-// columns' tables one column stride ((8 + D)(h+1) floats) apart.
-template <int S, int NCH>
-__global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(3))) void batch_pair_kernel(
-    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
-    unsigned int* counter, float* scratch, long long scratch_stride, int hmax) {
-    __shared__ int16_t qs2[2 * 64 * S];
-    __shared__ float qtab2[2 * 256];
-    __shared__ ColumnLds<S, 1> lds;
-    const int lane = threadIdx.x;
-    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
-    (void)hmax;
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = (int)atomicAdd(counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= ntasks) break;
-        const int2 tk = tasks[t];
-        const JobDesc& J = jobs[tk.x];
-        const int H = J.H, D = J.D, col0 = tk.y, stride = H + 1;
-        const bool has1 = col0 + 1 < J.ncols;
-        const long long colstride = (long long)(8 + D) * stride;
-        int fmin0, fmax0, fmin1, fmax1;
-        column_tables<S>(J, col0, true, qs2, ws, 8 * stride, fmin0, fmax0);
-        column_tables<S>(J, col0 + 1, has1, qs2 + 64 * S, ws + colstride, 8 * stride, fmin1,
-                         fmax1);
-        __syncthreads();   // the tables written above are read back below
-
-        ColumnIn in0, in1;
-        for (int x = 0; x < 2; ++x) {
-            ColumnIn& in = x ? in1 : in0;
-            float* base = ws + x * colstride;
-            in.PG = base;
-            in.PS = base + stride;
-            in.PA = base + 2 * stride;
-            in.PN2 = base + 3 * stride;
-            in.rowc = base + 4 * stride;
-            in.PO = base + 8 * stride;
-            in.fbase = x ? fmin1 : fmin0;
-            in.fmax = x ? fmax1 : fmax0;
-            in.q = qs2 + x * 64 * S;
-            in.O_df = J.object_df;
-            in.D = D;
-            in.fg_hi = J.fg_hi;
-            in.fg_lo = J.fg_lo;
-        }
-        ColumnOut out0, out1;
-        for (int x = 0; x < 2; ++x) {
-            ColumnOut& out = x ? out1 : out0;
-            const int col = col0 + x;
-            out.count = J.counts + col;
-            out.rec = J.records + (size_t)col * J.cap * 3;
-            out.total = J.total + col;
-            out.overflow = J.overflow + col;
-            out.cap = J.cap;
-        }
-        solve_pair<S, NCH>(H, J.vtop, J.prior, in0, in1, out0, out1, has1, qs2, qtab2, lds);
-        __syncthreads();   // every read of the slot completes before the next task rewrites it
-    }
-}
-
-void* batch_pair_kernel_for(int slots, int nch) {
-#define STX_CASE(n, c) \
-    if (slots == n && nch == c) return reinterpret_cast<void*>(&batch_pair_kernel<n, c>);
-    STX_FOR_EACH_PAIR_VARIANT(STX_CASE)
-#undef STX_CASE
-    return nullptr;
-}
 
 hipError_t launch_pair_batch(int slots, int nch, int grid, hipStream_t st, const JobDesc* jobs,
                              const int2* tasks, int ntasks, unsigned int* counter, float* scratch,
                              long long stride, int hmax) {
+    const void* f = batch_pair_kernel_ptr(slots, nch);
+    if (!f) return hipErrorInvalidValue;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-    bool launched = false;
-#define STX_CASE(n, c)                                                                       \
-    if (slots == n && nch == c) {                                                            \
-        hipLaunchKernelGGL((batch_pair_kernel<n, c>), dim3(grid), dim3(64), 0, st, jobs, tasks, \
-                           ntasks, counter, scratch, stride, hmax);                          \
-        launched = true;                                                                     \
-    }
-    STX_FOR_EACH_PAIR_VARIANT(STX_CASE)
-#undef STX_CASE
-    if (!launched) return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-void* batch_kernel_for(int slots, int nch, int waves) {
-#define STX_CASE(n, c, w) \
-    if (slots == n && nch == c && waves == w) return reinterpret_cast<void*>(&batch_kernel<n, c, w>);
-    STX_FOR_EACH_VARIANT(STX_CASE)
-#undef STX_CASE
-    return nullptr;
+    void* args[] = {&jobs, &tasks, &ntasks, &counter, &scratch, &stride, &hmax};
+    return hipLaunchKernel(f, dim3(grid), dim3(64), args, 0, st);
 }
 
 hipError_t launch_batch(int slots, int nch, int waves, int grid, hipStream_t st,
                         const JobDesc* jobs, const int2* tasks, int ntasks, unsigned int* counter,
                         float* scratch, long long stride, int hmax) {
+    const void* f = batch_kernel_ptr(slots, nch, waves);
+    if (!f) return hipErrorInvalidValue;
     // stagger the XCDs' starts only where the tasks fill two rounds or more
     // of the resident workgroups (a shorter launch would only be delayed)
-    const unsigned int stagger = (ntasks >= 2 * grid) ? kXcdStaggerCycles : 0u;
+    unsigned int stagger = (ntasks >= 2 * grid) ? kXcdStaggerCycles : 0u;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, counter);
-    bool launched = false;
-#define STX_CASE(n, c, w)                                                                    \
-    if (slots == n && nch == c && waves == w) {                                              \
-        hipLaunchKernelGGL((batch_kernel<n, c, w>), dim3(grid), dim3(64 * w), 0, st, jobs,   \
-                           tasks, ntasks, counter, scratch, stride, hmax, stagger);          \
-        launched = true;                                                                     \
-    }
-    STX_FOR_EACH_VARIANT(STX_CASE)
-#undef STX_CASE
-    if (!launched) return hipErrorInvalidValue;
-    return hipGetLastError();
+    void* args[] = {&jobs, &tasks, &ntasks, &counter, &scratch, &stride, &hmax, &stagger};
+    return hipLaunchKernel(f, dim3(grid), dim3(64 * waves), args, 0, st);
 }
 
 }  // namespace stx::persist
@@ -555,7 +88,7 @@ int batch_waves_for(const stixels_batch* b, int slots) {
 
 int occupancy_grid(stixels_batch* b, int slots, int nch, int waves, int* grid) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_for(slots, nch, waves),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_ptr(slots, nch, waves),
                                                      64 * waves, 0) != hipSuccess ||
         per_cu < 1)
         return bfail(b, STIXELS_E_HIP, "occupancy query failed");
@@ -598,31 +131,9 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return jobs[a].height > jobs[c].height; });
     int t = 0;
-    for (int i = 0; i < n; ++i) {
-        const stixels_job& j = jobs[i];
-        const stixels_handle* h = j.handle;
-        JobDesc& d = b->h_jobs[i];
-        d.disp = j.d_disparity;
-        d.sky = h->d_sky;
-        d.ground = h->d_ground;
-        d.object_t = h->d_object_t;
-        d.object_df = h->d_object_df;
-        d.fg_hi = h->d_fg_hi;
-        d.fg_lo = h->d_fg_lo;
-        d.counts = j.out.counts;
-        d.records = reinterpret_cast<uint32_t*>(j.out.records);
-        d.total = j.out.total_cost;
-        d.overflow = j.out.overflow;
-        d.W = j.width;
-        d.H = j.height;
-        d.s = h->s;
-        d.ncols = j.width / h->s;
-        d.D = h->D;
-        d.vtop = ground_top(h->p.camera.horizon_row, j.height);
-        d.reduce_mode = h->p.reduce_mode;
-        d.cap = j.out.capacity;
-        d.prior = h->prior;
-    }
+    for (int i = 0; i < n; ++i)
+        b->h_jobs[i] = make_job_desc(jobs[i].handle, jobs[i].d_disparity, jobs[i].width,
+                                     jobs[i].height, jobs[i].out);
     // two columns per wave only where that kernel exists (h <= 512,
     // d_range <= 128); a task is then a (frame, even column) pair
     const bool pairs = want_pairs && kernel_slots(hmax) <= 8 && kernel_chunks(dmax) == 2;
@@ -642,7 +153,7 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
 
 int pair_occupancy_grid(stixels_batch* b, int slots, int nch, int* grid) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pair_kernel_for(slots, nch), 64,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_pair_kernel_ptr(slots, nch), 64,
                                                      0) != hipSuccess ||
         per_cu < 1)
         return bfail(b, STIXELS_E_HIP, "occupancy query failed");
@@ -862,11 +373,68 @@ int stixels_batch_set_columns(stixels_batch* b, int32_t columns) {
 
 int stixels_batch_columns(const stixels_batch* b) { return b ? b->last_columns : 0; }
 
+int stixels_batch_device_bytes(const stixels_batch* b, size_t* bytes) {
+    if (!b || !bytes) return STIXELS_E_INVALID_ARG;
+    *bytes = 2 * (sizeof(JobDesc) * (size_t)b->cfg.max_jobs +
+                  sizeof(int2) * (size_t)b->cfg.max_tasks + sizeof(unsigned int)) +
+             sizeof(float) * b->scratch_floats + kTableGuardBytes;
+    return STIXELS_OK;
+}
+
 int stixels_batch_info(const stixels_batch* b, int32_t* workgroups, int32_t* tasks) {
     if (!b) return STIXELS_E_INVALID_ARG;
     if (workgroups) *workgroups = b->last_grid;
     if (tasks) *tasks = b->last_tasks;
     return STIXELS_OK;
+}
+
+int stixels_compute_batch(const stixels_job* jobs, int32_t n, void* stream) {
+    if (!jobs || n < 1 || !jobs[0].handle) return STIXELS_E_INVALID_ARG;
+    stixels_handle* owner = jobs[0].handle;
+    int hmax = 1, dmax = 2;
+    long long tasks = 0;
+    for (int i = 0; i < n; ++i) {
+        const stixels_handle* h = jobs[i].handle;
+        if (!h || jobs[i].width < h->s || jobs[i].height < 1 || jobs[i].height > h->Hmax) {
+            owner->err = "job " + std::to_string(i) + ": null handle or size outside its limits";
+            return STIXELS_E_INVALID_ARG;
+        }
+        hmax = std::max(hmax, (int)jobs[i].height);
+        dmax = std::max(dmax, h->D);
+        tasks += jobs[i].width / h->s;
+    }
+    if (tasks > INT_MAX) {
+        owner->err = "too many frame columns in one call";
+        return STIXELS_E_INVALID_ARG;
+    }
+    stixels_batch* b = owner->auto_batch;
+    if (!b || b->cfg.max_jobs < n || b->cfg.max_tasks < tasks || b->cfg.max_height < hmax ||
+        b->cfg.max_disparity < dmax) {
+        // grow: the new limits cover this call and every earlier one
+        stixels_batch_config c{};
+        c.max_jobs = b ? std::max((int)n, (int)b->cfg.max_jobs) : n;
+        c.max_tasks = (int)(b ? std::max<long long>(tasks, b->cfg.max_tasks) : tasks);
+        c.max_height = b ? std::max(hmax, (int)b->cfg.max_height) : hmax;
+        c.max_disparity = b ? std::max(dmax, (int)b->cfg.max_disparity) : dmax;
+        if (b) {
+            // earlier launches may still read the old batch's buffers
+            if (hipDeviceSynchronize() != hipSuccess) {
+                owner->err = "synchronising before growing the batch failed";
+                return STIXELS_E_HIP;
+            }
+            stixels_batch_destroy(b);
+            owner->auto_batch = nullptr;
+        }
+        const int rc = stixels_batch_create(&c, &b);
+        if (rc != STIXELS_OK) {
+            owner->err = "creating the batch of stixels_compute_batch failed";
+            return rc;
+        }
+        owner->auto_batch = b;
+    }
+    const int rc = stixels_batch_compute(b, jobs, n, stream);
+    if (rc != STIXELS_OK) owner->err = b->err;
+    return rc;
 }
 
 const char* stixels_batch_last_error(const stixels_batch* b) {

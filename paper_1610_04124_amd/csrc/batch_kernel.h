@@ -1,0 +1,457 @@
+// batch_kernel.h -- the persistent fused kernel of the batched launch.
+//
+// Every (frame, column) pair is a task.  The host orders tasks by decreasing
+// frame height (the recurrence costs O(h^2) per column, Sec. 3.3), so the
+// longest columns start first, and resident workgroups pull tasks from a
+// device counter until the list is exhausted.  Each task runs the whole
+// per-column pipeline of Sec. 4 without leaving the workgroup: strip
+// reduction into LDS, the prefix tables and object prefix rows into the
+// workgroup's own scratch slot (written and re-read by the same workgroup,
+// so they stay in L2), then the recurrence and backtracking of dp_column.h.
+// Results are bit-identical to the per-frame kernels: the arithmetic is the
+// same exact grid arithmetic, only the schedule differs.
+//
+// The templates are instantiated per slot count in the inst_s*.hip units
+// (kernel_table.h), so that the variants compile in parallel.
+#pragma once
+
+#include <climits>
+
+#include "dp_column.h"
+
+namespace stx {
+
+// A named namespace (not an anonymous one) so that profilers show the
+// kernels by name.
+namespace persist {
+
+struct JobDesc {
+    const float* disp;
+    const float* sky;
+    const float* ground;
+    const float* object_t;
+    const float* object_df;
+    const int32_t* fg_hi;
+    const int32_t* fg_lo;
+    int32_t* counts;
+    uint32_t* records;
+    float* total;
+    uint8_t* overflow;
+    int W, H, s, ncols, D, vtop, reduce_mode, cap;
+    Prior prior;
+};
+
+__device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D) {
+    switch (s) {
+#define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D);
+        STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
+        STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
+        STX_CASE(14) STX_CASE(15) STX_CASE(16)
+#undef STX_CASE
+        default: return -1;
+    }
+}
+
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Start delay between consecutive XCDs of a long batched launch, in shader
+// clock cycles (~5 us).
+constexpr unsigned int kXcdStaggerCycles = 10000u;
+
+// Waves per SIMD the register allocation of each variant is held to (the
+// compiler's own choice leaves a few registers above the next step down;
+// multi-wave workgroups keep a little more room for the row broadcast).
+constexpr int batch_waves(int slots_per_wave, int waves) {
+    return slots_per_wave <= 7 ? (waves == 1 ? 5 : 4) : (slots_per_wave <= 14 ? 3 : 2);
+}
+
+// One workgroup of W waves per column task.
+template <int S, int NCH, int W>
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch_kernel(
+    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
+    unsigned int* counter, float* scratch, long long scratch_stride, int hmax,
+    unsigned int stagger) {
+    __shared__ ColumnLds<S, W, 64 * NCH> lds;
+    // the column's reduced pixels live in the object row-cost array, which
+    // solve_column writes only after its last read of them
+    int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
+    __shared__ int task_slot;
+    __shared__ int red[3][W];
+    const int lane = threadIdx.x & 63;
+    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+    (void)hmax;
+    // Workgroups are dispatched to the eight XCDs in turn.  When every
+    // column takes equally long, all of them would reach the memory-heavy
+    // table builds together, round after round; starting XCD x stagger * x
+    // cycles late spreads those bursts over the shared memory system
+    // (measured: 2 % at 1024x440, insensitive to the delay's size).
+    if (stagger != 0u) {
+        const unsigned int xcd = blockIdx.x & 7u;
+        const unsigned long long t0 = __builtin_amdgcn_s_memtime();
+        const unsigned long long dl = (unsigned long long)xcd * stagger;
+        while (__builtin_amdgcn_s_memtime() - t0 < dl) __builtin_amdgcn_s_sleep(127);
+    }
+    for (;;) {
+        int t = 0;
+        if constexpr (W == 1) {
+            if (lane == 0) t = (int)atomicAdd(counter, 1u);
+            t = __builtin_amdgcn_readfirstlane(t);
+        } else {
+            if (threadIdx.x == 0) task_slot = (int)atomicAdd(counter, 1u);
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(task_slot);
+        }
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        const JobDesc& J = jobs[tk.x];
+        const int H = J.H, D = J.D, col = tk.y, stride = H + 1;
+
+        // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
+        int lmin = INT_MAX, lmax = -1;
+        bool inv = false;
+        for (int v = threadIdx.x; v < H; v += 64 * W) {
+            const int r = H - 1 - v;
+            const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
+                                     J.reduce_mode, D);
+            qs[v] = (int16_t)x;
+            if (x >= 0) {
+                lmin = min(lmin, x);
+                lmax = max(lmax, x);
+            } else {
+                inv = true;
+            }
+        }
+        // object means lie in [smallest, largest valid q]; a stixel without
+        // valid pixels has mean 0, so the table starts at 0 when the column
+        // holds an invalid pixel
+        int anyinv = __ballot(inv) ? 1 : 0;
+        int fmin = wave_min_i(lmin);
+        int fmax = wave_max_i(lmax);
+        if constexpr (W > 1) {
+            if (lane == 0) {
+                red[0][wave] = fmin;
+                red[1][wave] = fmax;
+                red[2][wave] = anyinv;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                fmin = min(fmin, red[0][w]);
+                fmax = max(fmax, red[1][w]);
+                anyinv |= red[2][w];
+            }
+        }
+        if (anyinv) fmin = 0;
+        if (fmax < 0) {
+            fmin = 0;
+            fmax = 0;
+        }
+        // the same in every lane; reading them from the first lane lets the
+        // compiler keep them (and the row offsets derived from them) scalar
+        fmin = __builtin_amdgcn_readfirstlane(fmin);
+        fmax = __builtin_amdgcn_readfirstlane(fmax);
+        __syncthreads();
+
+        // Sec. 4.2: prefix tables into the scratch slot: the four small ones
+        // by wave 0, the object rows f = fmin + wave, fmin + wave + W, ...
+        // Every load of a table row (one per 64-row slot) is issued before
+        // its scan starts, so a row costs one memory latency rather than one
+        // per slot.
+        float* PG = ws;
+        float* PS = ws + stride;
+        float* PA = ws + 2 * stride;
+        float* PN = ws + 3 * stride;
+        float* PO = ws + 4 * stride;
+        const int nsl = (H + 63) >> 6;
+        auto q_at = [&](int c) {
+            const int v = 64 * c + lane;
+            return (v < H) ? (int)qs[v] : -1;
+        };
+        if (wave == 0) {
+            if (lane == 0) {
+                PG[0] = 0.0f;
+                PS[0] = 0.0f;
+                PA[0] = 0.0f;
+                PN[0] = 0.0f;
+            }
+            float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+            for (int c = 0; c < nsl; ++c) {
+                const int v = 64 * c + lane, x = q_at(c);
+                float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+                if (x >= 0) {
+                    g = J.ground[(size_t)(H - 1 - v) * D + x];
+                    sk = J.sky[x];
+                    aa = (float)(2 * x + 1);
+                    nn = 2.0f;
+                }
+                g = wave_inclusive_scan(g) + cg;
+                sk = wave_inclusive_scan(sk) + cs;
+                aa = wave_inclusive_scan(aa) + ca;
+                nn = wave_inclusive_scan(nn) + cn;
+                if (v < H) {
+                    PG[v + 1] = g;
+                    PS[v + 1] = sk;
+                    PA[v + 1] = aa;
+                    PN[v + 1] = nn;
+                }
+                cg = readlane_f(g, 63);
+                cs = readlane_f(sk, 63);
+                ca = readlane_f(aa, 63);
+                cn = readlane_f(nn, 63);
+            }
+        }
+        const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+        // the column's object rows, stored through one buffer resource with a
+        // per-lane offset and the row's offset in a scalar register
+        const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+        // Byte offset of each slot's pixel within an object-cost row (2^30
+        // for an invalid pixel or a row past H: in the per-lane offset, which
+        // the bounds check always covers, so such lanes read 0); a row's
+        // offset is then the scalar part of every load.
+        uint32_t qoff[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int x = q_at(c);
+            qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+        }
+        // With several waves per column the loads of row f + W are in flight
+        // while row f is scanned; one-wave workgroups have no registers to
+        // spare for it (measured: double buffering made them spill and run
+        // slower) and load each row just before scanning it.
+        constexpr bool DB = (W > 1);
+        float oc[S], on[S];
+        auto load_row = [&](float (&o)[S], int f) {
+            const uint32_t rowb = (uint32_t)(f * D) * 4u;
+#pragma unroll
+            for (int c = 0; c < S; ++c) o[c] = buf_load_b(otr, qoff[c], rowb);
+        };
+        if constexpr (DB) {
+            if (fmin + wave <= fmax) load_row(oc, fmin + wave);
+        }
+#pragma unroll 1
+        for (int f = fmin + wave; f <= fmax; f += W) {
+            if constexpr (DB) {
+                if (f + W <= fmax) load_row(on, f + W);
+            } else {
+                load_row(oc, f);
+            }
+            const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
+            if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
+            // slots past H load zeros and store nothing: no per-slot branch,
+            // so the slots' scans can interleave
+            float carry = 0.0f;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                const int v = 64 * c + lane;
+                const float o = wave_inclusive_scan(oc[c]) + carry;
+                if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
+                carry = readlane_f(o, 63);
+            }
+            if constexpr (DB) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) oc[c] = on[c];
+            }
+        }
+        __syncthreads();   // the tables written above are read back below, by every wave
+
+        // Sec. 4.3-4.4
+        ColumnIn in;
+        in.PG = PG;
+        in.PS = PS;
+        in.PA = PA;
+        in.PN2 = PN;
+        in.PO = PO;
+        in.fbase = fmin;
+        in.fmax = fmax;
+        in.q = qs;
+        in.O_df = J.object_df;
+        in.D = D;
+        in.fg_hi = J.fg_hi;
+        in.fg_lo = J.fg_lo;
+        ColumnOut out;
+        out.count = J.counts + col;
+        out.rec = J.records + (size_t)col * J.cap * 3;
+        out.total = J.total + col;
+        out.overflow = J.overflow + col;
+        out.cap = J.cap;
+        solve_column<S, NCH, W>(H, J.vtop, J.prior, in, out, lds);
+        __syncthreads();   // every read of the slot completes before the next task rewrites it
+    }
+}
+
+// Sec. 4.1-4.2 for one column by one wave: its strips reduced into qs (LDS,
+// bottom-up; -1 past H and for a column that does not exist), then its
+// prefix tables at ws (PG, PS, PA, PN at 0..3 (h+1), the object rows from
+// po_at floats on).  Returns the column's disparity range [fmin, fmax].
+template <int S>
+__device__ void column_tables(const JobDesc& J, const int col, const bool exists, int16_t* qs,
+                              float* ws, const int po_at, int& fmin_out, int& fmax_out) {
+    const int lane = threadIdx.x & 63;
+    const int H = J.H, D = J.D, stride = H + 1;
+    int lmin = INT_MAX, lmax = -1;
+    bool inv = false;
+    for (int v = lane; v < 64 * S; v += 64) {
+        int x = -1;
+        if (exists && v < H)
+            x = reduce_any(J.disp + (size_t)(H - 1 - v) * J.W + (size_t)col * J.s, J.s,
+                           J.reduce_mode, D);
+        qs[v] = (int16_t)x;
+        if (x >= 0) {
+            lmin = min(lmin, x);
+            lmax = max(lmax, x);
+        } else if (v < H) {
+            inv = true;
+        }
+    }
+    int fmin = __ballot(inv) ? 0 : wave_min_i(lmin);
+    int fmax = wave_max_i(lmax);
+    if (fmax < 0) {
+        fmin = 0;
+        fmax = 0;
+    }
+    fmin = __builtin_amdgcn_readfirstlane(fmin);
+    fmax = __builtin_amdgcn_readfirstlane(fmax);
+    fmin_out = fmin;
+    fmax_out = fmax;
+    __syncthreads();
+    float* PG = ws;
+    float* PS = ws + stride;
+    float* PA = ws + 2 * stride;
+    float* PN = ws + 3 * stride;
+    if (lane == 0) {
+        PG[0] = 0.0f;
+        PS[0] = 0.0f;
+        PA[0] = 0.0f;
+        PN[0] = 0.0f;
+    }
+    float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+    for (int base = 0; base < H; base += 64) {
+        const int v = base + lane;
+        const int x = (v < H) ? (int)qs[v] : -1;
+        float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+        if (x >= 0) {
+            g = J.ground[(size_t)(H - 1 - v) * D + x];
+            sk = J.sky[x];
+            aa = (float)(2 * x + 1);
+            nn = 2.0f;
+        }
+        g = wave_inclusive_scan(g) + cg;
+        sk = wave_inclusive_scan(sk) + cs;
+        aa = wave_inclusive_scan(aa) + ca;
+        nn = wave_inclusive_scan(nn) + cn;
+        if (v < H) {
+            PG[v + 1] = g;
+            PS[v + 1] = sk;
+            PA[v + 1] = aa;
+            PN[v + 1] = nn;
+        }
+        cg = readlane_f(g, 63);
+        cs = readlane_f(sk, 63);
+        ca = readlane_f(aa, 63);
+        cn = readlane_f(nn, 63);
+    }
+    const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+    const auto pow_ =
+        make_rsrc(ws + po_at, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
+    uint32_t qoff[S];
+#pragma unroll
+    for (int c = 0; c < S; ++c) {
+        const int v = 64 * c + lane;
+        const int x = (v < H) ? (int)qs[v] : -1;
+        qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+    }
+#pragma unroll 1
+    for (int f = fmin; f <= fmax; ++f) {
+        const uint32_t rowb = (uint32_t)(f * D) * 4u;
+        float oc[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) oc[c] = buf_load_b(otr, qoff[c], rowb);
+        const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
+        if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
+        float carry = 0.0f;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const int v = 64 * c + lane;
+            const float o = wave_inclusive_scan(oc[c]) + carry;
+            if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
+            carry = readlane_f(o, 63);
+        }
+    }
+}
+
+// Two columns of one frame per one-wave workgroup (solve_pair): tasks are
+// (frame, even column) pairs.  The workgroup's scratch slot holds the two
+// columns' tables one column stride ((8 + D)(h+1) floats) apart.
+template <int S, int NCH>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(3))) void batch_pair_kernel(
+    const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
+    unsigned int* counter, float* scratch, long long scratch_stride, int hmax) {
+    __shared__ int16_t qs2[2 * 64 * S];
+    __shared__ float qtab2[2 * 256];
+    __shared__ ColumnLds<S, 1> lds;
+    const int lane = threadIdx.x;
+    float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
+    (void)hmax;
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = (int)atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntasks) break;
+        const int2 tk = tasks[t];
+        const JobDesc& J = jobs[tk.x];
+        const int H = J.H, D = J.D, col0 = tk.y, stride = H + 1;
+        const bool has1 = col0 + 1 < J.ncols;
+        const long long colstride = (long long)(8 + D) * stride;
+        int fmin0, fmax0, fmin1, fmax1;
+        column_tables<S>(J, col0, true, qs2, ws, 8 * stride, fmin0, fmax0);
+        column_tables<S>(J, col0 + 1, has1, qs2 + 64 * S, ws + colstride, 8 * stride, fmin1,
+                         fmax1);
+        __syncthreads();   // the tables written above are read back below
+
+        ColumnIn in0, in1;
+        for (int x = 0; x < 2; ++x) {
+            ColumnIn& in = x ? in1 : in0;
+            float* base = ws + x * colstride;
+            in.PG = base;
+            in.PS = base + stride;
+            in.PA = base + 2 * stride;
+            in.PN2 = base + 3 * stride;
+            in.rowc = base + 4 * stride;
+            in.PO = base + 8 * stride;
+            in.fbase = x ? fmin1 : fmin0;
+            in.fmax = x ? fmax1 : fmax0;
+            in.q = qs2 + x * 64 * S;
+            in.O_df = J.object_df;
+            in.D = D;
+            in.fg_hi = J.fg_hi;
+            in.fg_lo = J.fg_lo;
+        }
+        ColumnOut out0, out1;
+        for (int x = 0; x < 2; ++x) {
+            ColumnOut& out = x ? out1 : out0;
+            const int col = col0 + x;
+            out.count = J.counts + col;
+            out.rec = J.records + (size_t)col * J.cap * 3;
+            out.total = J.total + col;
+            out.overflow = J.overflow + col;
+            out.cap = J.cap;
+        }
+        solve_pair<S, NCH>(H, J.vtop, J.prior, in0, in1, out0, out1, has1, qs2, qtab2, lds);
+        __syncthreads();   // every read of the slot completes before the next task rewrites it
+    }
+}
+
+}  // namespace persist
+}  // namespace stx

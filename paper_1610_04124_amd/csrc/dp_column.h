@@ -316,8 +316,6 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
     const auto pgr = make_rsrc(in.PG, stride4);
     const auto psr = make_rsrc(in.PS, stride4);
-    const auto par = make_rsrc(in.PA, stride4);
-    const auto pnr = make_rsrc(in.PN2, stride4);
     float* const qtab = L.qtab[wave];
 
     // local slot t of this wave is global slot t W + wave

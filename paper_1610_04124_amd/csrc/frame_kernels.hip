@@ -6,12 +6,14 @@
 //                       sums and the object prefix table over the column's
 //                       own disparity range, with DPP wave scans;
 //   dp      (Sec. 4.3-4.4)  the recurrence and backtracking, one wave64 per
-//                       column (dp_column.h).
+//                       column (dp_kernel.h, instantiated in inst_s*.hip).
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
 
-#include "dp_column.h"
-
+#include "dp_kernel.h"
+#include "kernel_table.h"
 #include "launch.h"
 
 namespace stx {
@@ -183,95 +185,6 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
     }
 }
 
-// ------------------------------------------------------------------ dp
-struct DpArgs {
-    const int16_t* q;
-    const float* object_df;
-    const float* prefix;
-    const int32_t* range;
-    const float* po;
-    const int32_t* fg_hi;
-    const int32_t* fg_lo;
-    int32_t* counts;
-    uint32_t* records;
-    float* total;
-    uint8_t* overflow;
-    int cap, H, ncols, D, vtop;
-    int lds_floats;         // dynamic LDS of a POL launch, in floats
-    Prior prior;
-};
-
-// n floats from global memory into LDS by the W waves of the workgroup, and
-// a barrier.  The 16-byte-aligned body goes through direct global-to-LDS
-// loads (lane l of a wave fills bytes [16 l, 16 l + 16) above the wave's
-// LDS base; no register round trip, many loads in flight); the tail, and a
-// source that is not 16-byte aligned, through ordinary loads.  Nothing past
-// g[n-1] is read.
-template <int W>
-__device__ void copy_to_lds(float* lds, const float* g, int n) {
-    const int lane = threadIdx.x & 63;
-    const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    int done = 0;
-    if ((reinterpret_cast<uintptr_t>(g) & 15u) == 0) {
-        const int n4 = n & ~3;
-        for (int base = wave * 256; base < n4; base += 256 * W) {
-            const int i = base + 4 * lane;
-            if (i < n4)
-                __builtin_amdgcn_global_load_lds(g + i,
-                                                 (__attribute__((address_space(3))) void*)(lds + base),
-                                                 16, 0, 0);
-        }
-        done = n4;
-    }
-    for (int i = done + (int)threadIdx.x; i < n; i += 64 * W) lds[i] = g[i];
-    __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed
-    __syncthreads();
-}
-
-// One workgroup of W waves per column.  POL: the column's object prefix
-// table is copied into dynamic LDS when it fits (one copy, contiguous rows),
-// so that the recurrence gathers from LDS instead of the caches and HBM.
-template <int S, int NCH, int W, bool POL>
-__global__ __launch_bounds__(64 * W) void dp_kernel(DpArgs a) {
-    __shared__ ColumnLds<S, W, 64 * NCH> lds;
-    // the column's reduced pixels live in the object row-cost array, which
-    // solve_column writes only after its last read of them
-    int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
-    const int col = blockIdx.x;
-    const int stride = a.H + 1;
-    for (int v = threadIdx.x; v < a.H; v += 64 * W) qs[v] = a.q[(size_t)col * a.H + v];
-    __syncthreads();
-    ColumnIn in;
-    in.PG = a.prefix + ((size_t)0 * a.ncols + col) * stride;
-    in.PS = a.prefix + ((size_t)1 * a.ncols + col) * stride;
-    in.PA = a.prefix + ((size_t)2 * a.ncols + col) * stride;
-    in.PN2 = a.prefix + ((size_t)3 * a.ncols + col) * stride;
-    in.PO = a.po + (size_t)col * a.D * stride;
-    in.fbase = a.range[2 * col];
-    in.fmax = a.range[2 * col + 1];
-    in.q = qs;
-    in.O_df = a.object_df;
-    in.D = a.D;
-    in.fg_hi = a.fg_hi;
-    in.fg_lo = a.fg_lo;
-    ColumnOut out;
-    out.count = a.counts + col;
-    out.rec = a.records + (size_t)col * a.cap * 3;
-    out.total = a.total + col;
-    out.overflow = a.overflow + col;
-    out.cap = a.cap;
-    if constexpr (POL) {
-        extern __shared__ float po_lds[];
-        const int n = (in.fmax - in.fbase + 1) * stride;   // uniform over the workgroup
-        if (n <= a.lds_floats) {
-            copy_to_lds<W>(po_lds, in.PO, n);
-            solve_column<S, NCH, W, true, false>(a.H, a.vtop, a.prior, in, out, lds, po_lds);
-            return;
-        }
-    }
-    solve_column<S, NCH, W, false, false>(a.H, a.vtop, a.prior, in, out, lds);
-}
-
 // ------------------------------------------------------------------ self-test
 __global__ __launch_bounds__(256) void selftest_mean_kernel(int D, float eps,
                                                             unsigned long long* bad) {
@@ -356,42 +269,23 @@ namespace {
 
 // Largest POL dynamic LDS (bytes) of a variant on the current device, set
 // once per variant as the kernel's limit; 0 if the device refuses.
-template <int S, int NCH, int W>
-int pol_lds_bytes(int lds_per_block) {
-    static int bytes = -1;
-    if (bytes < 0) {
-        hipFuncAttributes fa{};
-        const void* f = reinterpret_cast<const void*>(&dp_kernel<S, NCH, W, true>);
-        int b = 0;
-        if (hipFuncGetAttributes(&fa, f) == hipSuccess) {
-            b = lds_per_block - (int)fa.sharedSizeBytes;
-            b = (b / 16) * 16;
-            if (b <= 0 || hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) !=
-                              hipSuccess)
-                b = 0;
-        }
-        bytes = b;
+int pol_lds_bytes(const void* f, int lds_per_block) {
+    static std::mutex mu;
+    static std::map<const void*, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(f);
+    if (it != cache.end()) return it->second;
+    hipFuncAttributes fa{};
+    int b = 0;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess) {
+        b = lds_per_block - (int)fa.sharedSizeBytes;
+        b = (b / 16) * 16;
+        if (b <= 0 ||
+            hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b) != hipSuccess)
+            b = 0;
     }
-    return bytes;
-}
-
-template <int S, int NCH, int W>
-void launch_dp_variant(const DpArgs& a0, bool pol, int lds_per_block, int ncols, hipStream_t st) {
-    DpArgs a = a0;
-    // the LDS copy is built for one wave per column and d_range <= 128 only:
-    // with both recurrences in one kernel the other variants run out of
-    // registers, and they were not faster with it
-    if constexpr (S <= 8 && NCH == 2 && W == 1) {
-        const int bytes = pol ? pol_lds_bytes<S, NCH, W>(lds_per_block) : 0;
-        if (bytes > 0) {
-            a.lds_floats = bytes / 4;
-            hipLaunchKernelGGL((dp_kernel<S, NCH, W, true>), dim3(ncols), dim3(64 * W),
-                               (size_t)bytes, st, a);
-            return;
-        }
-    }
-    a.lds_floats = 0;
-    hipLaunchKernelGGL((dp_kernel<S, NCH, W, false>), dim3(ncols), dim3(64 * W), 0, st, a);
+    cache[f] = b;
+    return b;
 }
 
 }  // namespace
@@ -425,16 +319,23 @@ hipError_t launch_dp(const DeviceModel& m, const FrameWorkspace& ws, int H, int 
     a.lds_floats = 0;
     a.prior = m.prior;
     const int slots = kernel_slots(H), nch = kernel_chunks(m.D);
-    bool launched = false;
-#define STX_CASE(n, c, w)                                                 \
-    if (slots == n && nch == c && waves == w) {                           \
-        launch_dp_variant<n, c, w>(a, po_lds, lds_per_block, ncols, st);  \
-        launched = true;                                                  \
+    // the LDS copy exists for one wave per column and d_range <= 128 only:
+    // with both recurrences in one kernel the other variants run out of
+    // registers, and they were not faster with it
+    if (po_lds) {
+        if (const void* f = dp_kernel_ptr(slots, nch, waves, true)) {
+            const int bytes = pol_lds_bytes(f, lds_per_block);
+            if (bytes > 0) {
+                a.lds_floats = bytes / 4;
+                void* args[] = {&a};
+                return hipLaunchKernel(f, dim3(ncols), dim3(64 * waves), args, (size_t)bytes, st);
+            }
+        }
     }
-    STX_FOR_EACH_VARIANT(STX_CASE)
-#undef STX_CASE
-    if (!launched) return hipErrorInvalidValue;
-    return hipGetLastError();
+    const void* f = dp_kernel_ptr(slots, nch, waves, false);
+    if (!f) return hipErrorInvalidValue;
+    void* args[] = {&a};
+    return hipLaunchKernel(f, dim3(ncols), dim3(64 * waves), args, 0, st);
 }
 
 hipError_t run_selftest_mean(int D, int max_height, int64_t* mismatches) {

@@ -16,6 +16,10 @@ struct stixels_handle {
     int waves = 0;          // waves per column of the recurrence (0 = automatic)
     int po_placement = 0;   // object prefix table of the recurrence: 0 auto, 1 HBM, 2 LDS
     int lds_per_block = 0;  // bytes
+    int frame_path = 0;     // stixels_compute: 0 auto, 1 staged kernels, 2 one fused launch
+    int last_path = 0;      // path of the last stixels_compute (1 or 2)
+    size_t ws_bytes = 0;    // bytes of d_po (the fused path's whole workspace)
+    stixels_batch* auto_batch = nullptr;   // batch object behind stixels_compute_batch
     // host copies of the rounded tables
     std::vector<float> sky, ground, object_t, object_df;
     std::vector<int32_t> fg_hi, fg_lo;

@@ -5,9 +5,10 @@ and offline tables resident in HBM).  Each request is admitted as soon as a
 launch slot and HBM are free for it, and every admitted request that is
 waiting when a launch slot frees up joins the next batched launch.  Launches
 go out on several streams, so a batch admitted while others run overlaps
-them on the device.  Admission charges each frame's HBM footprint (input,
-outputs, and the transient reduced column, prefix and object prefix tables)
-against a budget.  Latency is measured from arrival to completion.
+them on the device.  Admission charges each frame's HBM footprint (its input
+and outputs) against a budget from which the resident bytes (the cameras'
+tables and the batch objects' scratch) are taken once.  Latency is measured
+from arrival to completion.
 
 The loop is written against a small executor interface, so the admission
 and batching logic can run against a mock executor on the CPU; the GPU
@@ -31,13 +32,19 @@ class CameraSpec:
     def ncols(self) -> int:
         return self.width // self.handle.s
 
+    def height_class(self) -> int:
+        """64-row slots per lane of the recurrence: frames of one class share
+        a kernel variant and a batch object."""
+        return (self.height + 63) // 64
+
     def footprint(self) -> int:
-        """HBM bytes a frame of this camera holds while admitted."""
-        ncols, H, D = self.ncols(), self.height, self.handle.D
-        inp = 4 * self.width * H
-        out = ncols * (4 + 12 * H + 4 + 1)
-        transient = ncols * (2 * H + 4 * 4 * (H + 1) + 8 + 4 * D * (H + 1))
-        return inp + out + transient
+        """HBM bytes a frame of this camera holds while admitted: its input
+        and the outputs allocated for it.  The tables and scratch the
+        kernels use are resident (the handles' tables, the executor's batch
+        objects) and are charged once, not per frame."""
+        ncols, H = self.ncols(), self.height
+        cap = H
+        return 4 * self.width * H + ncols * (4 + 12 * cap + 4 + 1)
 
 
 @dataclass(eq=False)
@@ -57,7 +64,9 @@ class Request:
 
 
 class GpuExecutor:
-    """Batched launches on `streams` HIP streams, one batch object each."""
+    """Batched launches on `streams` HIP streams.  Every stream owns one batch
+    object per height class, so the launches of one admission (one per
+    class) never wait on each other's descriptor uploads."""
 
     def __init__(self, cameras, streams: int = 3, max_frames: int = 64):
         import torch
@@ -65,42 +74,57 @@ class GpuExecutor:
         import paper_1610_04124_amd as P
 
         self.cameras = cameras
-        hmax = max(c.height for c in cameras)
-        dmax = max(c.handle.D for c in cameras)
-        tmax = max_frames * max(c.ncols() for c in cameras)
         self.max_frames = max_frames
+        self.classes = {}
+        for c in cameras:
+            k = c.height_class()
+            hmax, dmax, cols = self.classes.get(k, (0, 0, 0))
+            self.classes[k] = (max(hmax, c.height), max(dmax, c.handle.D), max(cols, c.ncols()))
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.batches = [P.Batch(max_frames, tmax, hmax, dmax) for _ in range(streams)]
+        self.batches = [{k: P.Batch(max_frames, max_frames * cols, hmax, dmax)
+                         for k, (hmax, dmax, cols) in self.classes.items()}
+                        for _ in range(streams)]
         self.free = list(range(streams))
         self._torch = torch
         self._P = P
-        # waves per column of each height class (64-row slots); classes not
-        # tuned use one wave for up to 8 slots and two above, which is what
-        # the autotuner picks at 440 and 880 rows on MI355X
-        self.waves = {}
+        # launch layout of each height class: (columns per wave, waves per
+        # column, workgroups); untuned classes use one wave per column for
+        # up to 8 slots and two above, the autotuner's choice at 440 and 880
+        # rows on MI355X, and the occupancy limit
+        self.layout = {}
 
-    def waves_for(self, slots: int) -> int:
-        return self.waves.get(slots, 1 if slots <= 8 else 2)
+    def layout_for(self, k: int):
+        return self.layout.get(k, (1, 1 if k <= 8 else 2, 0))
+
+    def resident_bytes(self) -> int:
+        """Device bytes held for the whole run: the batch objects and the
+        cameras' handles (tables, and workspace unless batch-only)."""
+        n = sum(b.device_bytes() for per in self.batches for b in per.values())
+        seen = set()
+        for c in self.cameras:
+            if id(c.handle) not in seen:
+                seen.add(id(c.handle))
+                n += c.handle.device_bytes()
+        return n
 
     def tune(self, frames_by_camera, max_frames: int = 16):
-        """Time waves per column for every height class on sample frames
+        """Time the launch layout of every height class on sample frames
         (camera index -> list of device frames) and keep the fastest."""
         from paper_1610_04124_amd.autotune import tune
 
         st = self.streams[0]
-        classes = {}
+        members = {}
         for ci, frames in frames_by_camera.items():
             c = self.cameras[ci]
             for f in frames:
-                classes.setdefault((c.height + 63) // 64, []).append((c, f))
-        for slots, members in classes.items():
-            members = members[:max_frames]
-            items = [(c.handle, f, c.handle.new_output(c.width, c.height)) for c, f in members]
-            rec = tune(self.batches[0], items, st, replays=3, cache_path=None)
-            self.waves[slots] = rec["waves"]
-        self.batches[0].set_workgroups(0)
+                members.setdefault(c.height_class(), []).append((c, f))
+        for k, mem in members.items():
+            mem = mem[:max_frames]
+            items = [(c.handle, f, c.handle.new_output(c.width, c.height)) for c, f in mem]
+            rec = tune(self.batches[0][k], items, st, replays=3, cache_path=None)
+            self.layout[k] = (rec["columns"], rec["waves"], 0)
         self._torch.cuda.synchronize()
-        return dict(self.waves)
+        return {k: {"columns": v[0], "waves": v[1]} for k, v in self.layout.items()}
 
     def slots(self) -> int:
         return len(self.free)
@@ -109,9 +133,8 @@ class GpuExecutor:
         """Allocate the requests' outputs and enqueue the batched launches,
         all on one stream (the allocation's zero fill is stream-ordered before
         the kernels that write the results).  Frames are grouped by height
-        class (64-row slots per lane of the recurrence), one launch per
-        class, so short frames never run the register-heavy variant sized
-        for tall ones."""
+        class, one launch per class, so short frames never run the
+        register-heavy variant sized for tall ones."""
         i = self.free.pop()
         st = self.streams[i]
         with self._torch.cuda.stream(st):
@@ -120,11 +143,15 @@ class GpuExecutor:
                 r.out = c.handle.new_output(c.width, c.height)
         groups = {}
         for r in reqs:
-            groups.setdefault((self.cameras[r.camera].height + 63) // 64, []).append(r)
-        for slots in sorted(groups, reverse=True):
-            items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in groups[slots]]
-            self.batches[i].set_waves(self.waves_for(slots))
-            self.batches[i].compute(items, st)
+            groups.setdefault(self.cameras[r.camera].height_class(), []).append(r)
+        for k in sorted(groups, reverse=True):
+            items = [(self.cameras[r.camera].handle, r.frame, r.out) for r in groups[k]]
+            b = self.batches[i][k]
+            cols, waves, wg = self.layout_for(k)
+            b.set_columns(cols)
+            b.set_waves(waves)
+            b.set_workgroups(wg)
+            b.compute(items, st)
         ev = self._torch.cuda.Event()
         ev.record(st)
         return (i, ev)
@@ -141,10 +168,14 @@ class Server:
     """Admission by HBM footprint + continuous batching over an executor."""
 
     def __init__(self, cameras, executor, hbm_budget: int, max_batch: int = 64,
-                 clock=time.perf_counter, keep_outputs: bool = True):
+                 clock=time.perf_counter, keep_outputs: bool = True, resident_bytes: int = 0):
+        """hbm_budget covers everything the run holds on the device: the
+        resident bytes (tables and batch scratch, charged once) plus the
+        footprints of the admitted frames."""
         self.cameras = cameras
         self.ex = executor
-        self.budget = int(hbm_budget)
+        self.resident = int(resident_bytes)
+        self.budget = int(hbm_budget) - self.resident
         self.max_batch = int(max_batch)
         self.clock = clock
         self.queue = collections.deque()
@@ -156,10 +187,12 @@ class Server:
         self.launches = 0
         self.max_in_use = 0
         self.max_inflight = 0
+        self.max_queue = 0
         self.keep_outputs = keep_outputs
         for c in cameras:
             if c.footprint() > self.budget:
-                raise ValueError("HBM budget smaller than one frame of a camera")
+                raise ValueError("HBM budget smaller than the resident bytes plus one frame of "
+                                 "a camera")
 
     # ---------------------------------------------------------------- API
     def submit(self, camera: int, frame, arrival: float | None = None) -> Request | None:
@@ -175,6 +208,7 @@ class Server:
             self.rejected.append(r)
             return None
         self.queue.append(r)
+        self.max_queue = max(self.max_queue, len(self.queue))
         return r
 
     def cancel(self, req: Request) -> bool:
@@ -250,24 +284,30 @@ class Server:
 
     def stats(self) -> dict:
         lat = sorted(r.latency for r in self.completed)
+        wait = sorted(r.admitted - r.arrival for r in self.completed)
 
-        def pct(q):
-            if not lat:
+        def pct(xs, q):
+            if not xs:
                 return None
-            k = (len(lat) - 1) * q
+            k = (len(xs) - 1) * q
             lo = int(k)
-            hi = min(lo + 1, len(lat) - 1)
-            return lat[lo] + (lat[hi] - lat[lo]) * (k - lo)
+            hi = min(lo + 1, len(xs) - 1)
+            return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
         span = (max(r.done for r in self.completed) - min(r.arrival for r in self.completed)
                 if self.completed else 0.0)
+        ms = lambda x: None if x is None else 1e3 * x  # noqa: E731
         return {"completed": len(self.completed), "rejected": len(self.rejected),
                 "launches": self.launches,
                 "frames_per_launch": len(self.completed) / max(self.launches, 1),
                 "throughput_fps": len(self.completed) / span if span > 0 else None,
-                "latency_ms_p50": None if not lat else 1e3 * pct(0.5),
-                "latency_ms_p99": None if not lat else 1e3 * pct(0.99),
-                "peak_hbm_in_use": self.max_in_use, "max_launches_in_flight": self.max_inflight}
+                "latency_ms_p50": ms(pct(lat, 0.5)), "latency_ms_p99": ms(pct(lat, 0.99)),
+                "admission_wait_ms_p50": ms(pct(wait, 0.5)),
+                "admission_wait_ms_p99": ms(pct(wait, 0.99)),
+                "max_queue": self.max_queue,
+                "resident_bytes": self.resident, "budget_bytes": self.budget + self.resident,
+                "peak_admitted_bytes": self.max_in_use,
+                "max_launches_in_flight": self.max_inflight}
 
 
 def poisson_arrivals(rates, seconds: float, seeds, frames_per_camera: int):
@@ -295,7 +335,8 @@ SERVING_SIZES = [(1024, 440), (1280, 720), (2048, 880)]
 
 
 def serving_cameras(n_cameras: int = 8, stixel_width: int = 5):
-    """Handles and frame sizes of the serving workload (one handle per camera)."""
+    """Handles and frame sizes of the serving workload (one handle per camera,
+    used through the batch API only, so without a per-frame workspace)."""
     import synth
     import paper_1610_04124_amd as P
 
@@ -304,6 +345,7 @@ def serving_cameras(n_cameras: int = 8, stixel_width: int = 5):
         W, H = SERVING_SIZES[i % len(SERVING_SIZES)]
         D = 256 if W == 2048 else 128
         p = synth.make_params(camera=synth.camera_for_size(W, H), stixel_width=stixel_width,
-                              max_disparity=D, max_width=W, max_height=H)
+                              max_disparity=D, max_width=W, max_height=H,
+                              flags=P.binding.FLAG_BATCH_ONLY)
         cams.append(CameraSpec(P.Stixels(p), W, H))
     return cams
