@@ -54,7 +54,7 @@ class SoParams(C.Structure):
         ("ordering_tol_px", C.c_int32),
         ("stixel_width", C.c_int32), ("max_disparity", C.c_int32),
         ("max_stixels_per_column", C.c_int32), ("reduce_mode", C.c_int32),
-        ("cost_grid_log2", C.c_int32),
+        ("cost_grid_log2", C.c_int32), ("subpixel_log2", C.c_int32),
     ]
 
 
@@ -109,7 +109,13 @@ def to_struct(params: dict) -> SoParams:
     for k in ("stixel_width", "max_disparity", "max_stixels_per_column", "reduce_mode",
               "cost_grid_log2"):
         setattr(p, k, int(params[k]))
+    p.subpixel_log2 = int(params.get("subpixel_log2", 0))
     return p
+
+
+def bins(params: dict) -> int:
+    """Disparity bins: max_disparity px in bins of 2^-subpixel_log2 px."""
+    return int(params["max_disparity"]) << int(params.get("subpixel_log2", 0))
 
 
 def _ptr(a, ct):
@@ -132,8 +138,8 @@ def quantize(x: float, g: int) -> float:
 
 def tables(params: dict, H: int) -> dict:
     """Offline LUTs for a frame of height H: S[d], G[v, d] (bottom-up v),
-    O[d, f], fg_hi[b], fg_lo[b]."""
-    D = int(params["max_disparity"])
+    O[d, f], fg_hi[b], fg_lo[b]; d and f are disparity bins."""
+    D = bins(params)
     S = np.zeros(D, np.float64)
     G = np.zeros((H, D), np.float64)
     O = np.zeros((D, D), np.float64)
@@ -161,7 +167,7 @@ def column(params: dict, q_col) -> dict:
     """Solve one reduced column; returns every intermediate of the method."""
     q = np.ascontiguousarray(q_col, dtype=np.int32)
     H = int(q.shape[0])
-    D = int(params["max_disparity"])
+    D = bins(params)
     out = dict(
         PG=np.zeros(H + 1), PS=np.zeros(H + 1),
         PD=np.zeros(H + 1, np.int64), PN=np.zeros(H + 1, np.int64),

@@ -39,6 +39,13 @@
  *     by more than a tolerance;
  *   - every table value and prior constant is rounded to a multiple of
  *     2^-cost_grid_log2 nats (cost_grid_log2 < 0 disables the rounding);
+ *   - disparities may be resolved finer than 1 px: in bins of
+ *     2^-subpixel_log2 px, the reduced pixel is rint(value * 2^subpixel_log2),
+ *     object means are rounded to a bin, tables are evaluated at the bins'
+ *     disparities in px, the diving / gravity thresholds are floor / ceil of
+ *     the px bound times 2^subpixel_log2 and the ordering tolerance is
+ *     ordering_tol_px bins times 2^subpixel_log2 (the outlier density stays
+ *     uniform over [0, max_disparity] px);
  *   - ties go to the first candidate in the order of Eq. 6: the bottom-stixel
  *     candidate, then cut positions b ascending, then predecessor classes
  *     object, ground, sky; the final class is the first minimum in that order.
@@ -76,6 +83,12 @@ double so_quantize(double x, int32_t g)
 }
 
 /* ------------------------------------------------------------- Sec. 3.1 */
+
+/* Disparity bins: max_disparity px in bins of 2^-subpixel_log2 px.  A bin
+ * index i stands for the disparity i * 2^-subpixel_log2 px. */
+static int32_t n_bins(const so_params *p) { return p->max_disparity << p->subpixel_log2; }
+
+static double bin_px(const so_params *p, int32_t i) { return ldexp((double)i, -p->subpixel_log2); }
 
 /* Ground disparity slope in px per row, from the camera (slope and horizon are
  * known per image, Sec. 3). */
@@ -122,32 +135,34 @@ static double sigma_object(const so_params *p, double f)
 int so_tables(const so_params *p, int32_t H, double *S, double *G, double *O,
               int32_t *fg_hi, int32_t *fg_lo)
 {
-    if (!p || H < 1 || p->max_disparity < 1) return SO_EINVAL;
-    const int32_t D = p->max_disparity;
-    const double dr = (double)D;
+    if (!p || H < 1 || p->max_disparity < 1 || p->subpixel_log2 < 0 || p->subpixel_log2 > 3)
+        return SO_EINVAL;
+    const int32_t D = n_bins(p);
+    const double dr = (double)p->max_disparity;
     const int32_t g = p->cost_grid_log2;
     const int32_t vtop = ground_top(p, H);
 
     for (int32_t d = 0; d < D; ++d)
-        S[d] = so_quantize(so_pixel_cost(d, 0.0, p->sigma_sky, p->p_out, dr), g);
+        S[d] = so_quantize(so_pixel_cost(bin_px(p, d), 0.0, p->sigma_sky, p->p_out, dr), g);
 
     for (int32_t v = 0; v < H; ++v) {
         double mu = f_ground(p, H, v);
         for (int32_t d = 0; d < D; ++d)
             G[(size_t)v * D + d] = (v <= vtop)
-                ? so_quantize(so_pixel_cost(d, mu, sigma_ground(p, mu), p->p_out, dr), g)
+                ? so_quantize(so_pixel_cost(bin_px(p, d), mu, sigma_ground(p, mu), p->p_out, dr), g)
                 : 0.0;
     }
 
     for (int32_t d = 0; d < D; ++d)
         for (int32_t f = 0; f < D; ++f)
             O[(size_t)d * D + f] =
-                so_quantize(so_pixel_cost(d, f, sigma_object(p, f), p->p_out, dr), g);
+                so_quantize(so_pixel_cost(bin_px(p, d), bin_px(p, f),
+                                          sigma_object(p, bin_px(p, f)), p->p_out, dr), g);
 
     for (int32_t b = 0; b <= H; ++b) {
         double fg = f_ground(p, H, b);
-        fg_hi[b] = (int32_t)floor(fg + p->diving_tol_px);
-        fg_lo[b] = (int32_t)ceil(fg - p->gravity_tol_px);
+        fg_hi[b] = (int32_t)floor(ldexp(fg + p->diving_tol_px, p->subpixel_log2));
+        fg_lo[b] = (int32_t)ceil(ldexp(fg - p->gravity_tol_px, p->subpixel_log2));
     }
     return SO_OK;
 }
@@ -156,7 +171,7 @@ int so_tables(const so_params *p, int32_t H, double *S, double *G, double *O,
  * transposed and bottom-up (q[i*H + v], v = H-1-r). */
 int so_reduce(const so_params *p, const float *disp, int32_t W, int32_t H, int32_t *q)
 {
-    if (!p || !disp || !q) return SO_EINVAL;
+    if (!p || !disp || !q || p->subpixel_log2 < 0 || p->subpixel_log2 > 3) return SO_EINVAL;
     const int32_t s = p->stixel_width;
     if (s < 1 || W < s || H < 1) return SO_EINVAL;
     const int32_t ncols = W / s;
@@ -186,8 +201,8 @@ int so_reduce(const so_params *p, const float *disp, int32_t W, int32_t H, int32
                     for (int32_t a = 0; a < n; ++a) sum += vals[a];
                     m = sum / (double)n;
                 }
-                double rq = rint(m);
-                double top = (double)(p->max_disparity - 1);
+                double rq = rint(ldexp(m, p->subpixel_log2));
+                double top = (double)(n_bins(p) - 1);
                 out = (int32_t)(rq < top ? rq : top);
             }
             q[(size_t)i * H + (H - 1 - r)] = out;
@@ -268,7 +283,8 @@ static double prior_pair(const column_ctx *x, int32_t cp, int32_t c, int32_t f_p
     double t = x->T[cp][c];
     if (isinf(t)) return INFINITY;
     double pen = 0.0;
-    if (c == SO_OBJECT && cp == SO_OBJECT && f > f_prev + x->p->ordering_tol_px)
+    if (c == SO_OBJECT && cp == SO_OBJECT &&
+        f > f_prev + (x->p->ordering_tol_px << x->p->subpixel_log2))
         pen = x->c_ord;
     if (c == SO_OBJECT && cp == SO_GROUND) {
         if (f > x->fg_hi[b]) pen = x->c_dive;
@@ -345,6 +361,7 @@ static int validate(const so_params *p)
 {
     if (!p) return SO_EINVAL;
     if (p->max_disparity < 1 || p->stixel_width < 1) return SO_EINVAL;
+    if (p->subpixel_log2 < 0 || p->subpixel_log2 > 3) return SO_EINVAL;
     if (!(p->p_out > 0.0 && p->p_out < 1.0)) return SO_EINVAL;
     if (!(p->sigma_disp > 0.0 && p->sigma_sky > 0.0)) return SO_EINVAL;
     if (!(p->cam_height_m > 0.0 && p->focal_px > 0.0 && p->baseline_m > 0.0)) return SO_EINVAL;
@@ -360,7 +377,7 @@ static void fill_ctx(column_ctx *x, const so_params *p, int32_t H)
     const int32_t g = p->cost_grid_log2;
     x->p = p;
     x->H = H;
-    x->D = p->max_disparity;
+    x->D = n_bins(p);
     x->vtop = ground_top(p, H);
     for (int c = 0; c < NCLS; ++c) {
         x->F[c] = so_quantize(p->first_cost[c], g);
@@ -378,7 +395,7 @@ int so_column(const so_params *p, int32_t H, const int32_t *q,
               so_stixel *out, int32_t *n_out, double *total)
 {
     if (validate(p) != SO_OK || H < 1 || !q) return SO_EINVAL;
-    const int32_t D = p->max_disparity;
+    const int32_t D = n_bins(p);
     double *S = (double *)malloc(sizeof(double) * (size_t)D);
     double *G = (double *)malloc(sizeof(double) * (size_t)H * D);
     double *O = (double *)malloc(sizeof(double) * (size_t)D * D);
@@ -404,7 +421,7 @@ int so_frame(const so_params *p, const float *disp, int32_t W, int32_t H, int32_
              int32_t nthreads)
 {
     if (validate(p) != SO_OK || !disp || H < 1 || W < p->stixel_width) return SO_EINVAL;
-    const int32_t D = p->max_disparity;
+    const int32_t D = n_bins(p);
     const int32_t ncols = W / p->stixel_width;
     if (cap <= 0) cap = H;
     int32_t *q = (int32_t *)malloc(sizeof(int32_t) * (size_t)ncols * H);

@@ -9,6 +9,7 @@
  *
  * Conventions
  *   rows v are bottom-up inside a column (v = 0 is the bottom pixel, Sec. 3.1);
+ *   disparities are integer bins of 2^-subpixel_log2 px (1 px by default);
  *   classes are 0 = object, 1 = ground, 2 = sky (the order of the class set);
  *   all costs are negative log-likelihoods in nats.
  */
@@ -38,6 +39,10 @@ typedef struct {
     int32_t ordering_tol_px;
     /* geometry / numerics */
     int32_t stixel_width, max_disparity, max_stixels_per_column, reduce_mode, cost_grid_log2;
+    /* disparity bins of 2^-subpixel_log2 px (0..3): pixel disparities, object
+     * means and the rows of the object tables are bin indices; max_disparity
+     * stays in px, so there are max_disparity << subpixel_log2 bins */
+    int32_t subpixel_log2;
 } so_params;
 
 typedef struct {
@@ -50,12 +55,12 @@ double so_pixel_cost(double d, double mu, double sigma, double p_out, double d_r
 /* Rounding of a table value onto the cost grid, 2^-g nats (g < 0: identity). */
 double so_quantize(double x, int32_t g);
 
-/* Offline tables for a frame of height H (Sec. 3.4):
+/* Offline tables for a frame of height H (Sec. 3.4), D = number of bins:
  *   S[d]        sky cost,                                      D values
  *   G[v*D + d]  ground cost at bottom-up row v (0 above horizon), H*D values
  *   O[d*D + f]  object cost of pixel disparity d, mean f,      D*D values
- *   fg_hi[b], fg_lo[b]  integer diving / gravity thresholds for an object
- *               whose base is row b, b = 0..H                  H+1 values each */
+ *   fg_hi[b], fg_lo[b]  integer diving / gravity thresholds (in bins) for an
+ *               object whose base is row b, b = 0..H           H+1 values each */
 int so_tables(const so_params *p, int32_t H, double *S, double *G, double *O,
               int32_t *fg_hi, int32_t *fg_lo);
 

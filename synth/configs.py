@@ -66,7 +66,7 @@ def make_params(camera: dict | None = None, model: dict | None = None, *,
                 stixel_width: int = 5, max_disparity: int = 128,
                 max_width: int = 1024, max_height: int = 440,
                 max_stixels_per_column: int = 0, reduce_mode: int = 0,
-                cost_grid_log2: int = 10, flags: int = 0) -> dict:
+                cost_grid_log2: int = 10, flags: int = 0, subpixel_log2: int = 0) -> dict:
     """Full parameter set handed to both the oracle and the HIP library.
 
     reduce_mode: 0 = lower median of the valid pixels of each row strip,
@@ -76,6 +76,8 @@ def make_params(camera: dict | None = None, model: dict | None = None, *,
     max_stixels_per_column: output capacity per column, 0 means the height.
     flags: library handle flags (1 = batch API only: no per-frame workspace);
                  the oracle ignores them.
+    subpixel_log2: disparities in bins of 2^-subpixel_log2 px (0 = whole px);
+                 max_disparity stays in px.
     """
     return {
         "camera": dict(camera if camera is not None else CAMERA_1024x440),
@@ -88,6 +90,7 @@ def make_params(camera: dict | None = None, model: dict | None = None, *,
         "reduce_mode": int(reduce_mode),
         "cost_grid_log2": int(cost_grid_log2),
         "flags": int(flags),
+        "subpixel_log2": int(subpixel_log2),
     }
 
 

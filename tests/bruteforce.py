@@ -48,6 +48,8 @@ class Problem:
         self.c_ord = qz(self.m["ordering_cost"])
         self.c_grav = qz(self.m["gravity_cost"])
         self.c_dive = qz(self.m["diving_cost"])
+        # ordering tolerance in disparity bins (2^-subpixel_log2 px)
+        self.tau = int(self.m["ordering_tol_px"]) << int(params.get("subpixel_log2", 0))
 
     def mean(self, b, t):
         return rounded_mean([d for d in self.q[b:t + 1] if d >= 0])
@@ -79,7 +81,7 @@ class Problem:
         if math.isinf(tr):
             return math.inf
         pen = 0.0
-        if c == OB and prev[2] == OB and f > prev[3] + int(self.m["ordering_tol_px"]):
+        if c == OB and prev[2] == OB and f > prev[3] + self.tau:
             pen = self.c_ord
         if c == OB and prev[2] == GR:
             if f > self.t["fg_hi"][b]:
@@ -198,7 +200,7 @@ def c_map(build_dir: str, pb: Problem):
     P = lambda a, t: a.ctypes.data_as(C.POINTER(t))  # noqa: E731
     rc = L.bf_map(H, P(q, C.c_int32), D, P(G, C.c_double), P(S, C.c_double), P(O, C.c_double),
                   P(hi, C.c_int32), P(lo, C.c_int32), int(pb.vtop), P(F, C.c_double),
-                  P(T, C.c_double), pb.beta, pb.c_ord, int(pb.m["ordering_tol_px"]), pb.c_grav,
+                  P(T, C.c_double), pb.beta, pb.c_ord, int(pb.tau), pb.c_grav,
                   pb.c_dive, C.byref(best), P(path, C.c_int32), C.byref(npath), C.byref(nl),
                   C.byref(no))
     if rc != 0:

@@ -45,7 +45,8 @@ class NaiveColumn:
         self.c_ord = q_grid(m["ordering_cost"], g)
         self.c_grav = q_grid(m["gravity_cost"], g)
         self.c_dive = q_grid(m["diving_cost"], g)
-        self.tau = int(m["ordering_tol_px"])
+        # ordering tolerance in disparity bins of 2^-subpixel_log2 px
+        self.tau = int(m["ordering_tol_px"]) << int(params.get("subpixel_log2", 0))
 
     def mean(self, b: int, k: int) -> int:
         vals = [d for d in self.q[b:k + 1] if d >= 0]

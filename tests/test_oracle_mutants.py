@@ -17,6 +17,7 @@ import pytest
 import oracle
 import test_oracle_exhaustive as EX
 import test_oracle_pins as PIN
+import test_oracle_subpixel as SUB
 from naive_dp import NaiveColumn
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
@@ -32,12 +33,20 @@ MUTANTS = [
     ("object table transposed", "(valid ? x->O[(size_t)d * D + f] : 0.0)",
      "(valid ? x->O[(size_t)f * D + d] : 0.0)"),
     ("mean truncated instead of rounded", "(2 * sum + n) / (2 * n)", "(2 * sum) / (2 * n)"),
-    ("diving threshold off by one", "floor(fg + p->diving_tol_px);",
-     "floor(fg + p->diving_tol_px) + 1;"),
-    ("gravity threshold rounded down", "ceil(fg - p->gravity_tol_px);",
-     "floor(fg - p->gravity_tol_px);"),
-    ("ordering comparison not strict", "f > f_prev + x->p->ordering_tol_px",
-     "f >= f_prev + x->p->ordering_tol_px"),
+    ("diving threshold off by one", "floor(ldexp(fg + p->diving_tol_px, p->subpixel_log2));",
+     "floor(ldexp(fg + p->diving_tol_px, p->subpixel_log2)) + 1;"),
+    ("gravity threshold rounded down", "ceil(ldexp(fg - p->gravity_tol_px, p->subpixel_log2));",
+     "floor(ldexp(fg - p->gravity_tol_px, p->subpixel_log2));"),
+    ("ordering comparison not strict", "f > f_prev + (x->p->ordering_tol_px",
+     "f >= f_prev + (x->p->ordering_tol_px"),
+    ("ordering tolerance not in bins", "(x->p->ordering_tol_px << x->p->subpixel_log2)",
+     "x->p->ordering_tol_px"),
+    ("thresholds not in bins", "floor(ldexp(fg + p->diving_tol_px, p->subpixel_log2));",
+     "floor(fg + p->diving_tol_px);"),
+    ("object table at bin indices, not px", "sigma_object(p, bin_px(p, f)), p->p_out, dr), g);",
+     "sigma_object(p, f), p->p_out, dr), g);"),
+    ("reduction not scaled to bins", "double rq = rint(ldexp(m, p->subpixel_log2));",
+     "double rq = rint(m);"),
     ("gravity comparison not strict", "else if (f < x->fg_lo[b])", "else if (f <= x->fg_lo[b])"),
     ("diving comparison not strict", "if (f > x->fg_hi[b]) pen", "if (f >= x->fg_hi[b]) pen"),
     ("diving and gravity costs swapped",
@@ -130,6 +139,9 @@ BATTERY = [
     ("brute force, ordering off", lambda: [PIN.test_dp_equals_bruteforce_map_without_ordering(H, g)
                                            for H in (5, 7) for g in (10, 0)]),
     ("naive recurrence", naive_battery),
+    ("bins: reduction", lambda: [SUB.test_reduce_in_bins(sp, m) for sp in (1, 2) for m in (0, 1)]),
+    ("bins: tables", lambda: SUB.test_tables_in_bins_against_scipy(1)),
+    ("bins: naive recurrence", lambda: SUB.test_naive_recurrence_in_bins(1)),
 ]
 
 
