@@ -85,6 +85,13 @@ typedef struct {
     int32_t reduce_mode;         /* 0 = lower median of the valid pixels, 1 = mean (Sec. 4.1) */
     int32_t cost_grid_log2;      /* g: costs are multiples of 2^-g nats, 0..12 */
     int32_t flags;               /* STIXELS_FLAG_* bits, 0 = none */
+    int32_t subpixel_log2;       /* k, 0..3: disparities in bins of 2^-k px (Sec. 3.4 rounds
+                                    pixels and object means to whole px; k > 0 resolves them
+                                    finer).  Reduced pixels, object means, the record's
+                                    disparity and the table rows are bin indices; Eq. 4 is
+                                    evaluated at the bins' disparities in px.  There are
+                                    max_disparity << k bins, at most 256. */
+    int32_t reserved1;
 } stixels_params;
 
 /* stixels_params.flags: the handle is used only through the batch API
@@ -118,6 +125,21 @@ typedef struct {
 } stixels_output;
 
 typedef struct stixels_handle stixels_handle;
+
+/* Camera pose of one frame.  The paper takes the ground slope and the
+ * horizon as known for each image (Sec. 3); a frame that brings its own pose
+ * is segmented with the ground model of that pose instead of the handle's
+ * camera: slope baseline * cos(pitch_rad) / cam_height (focal, baseline and
+ * height stay the handle's), horizon at top-down row horizon_row.  The
+ * handle's ground table (Eq. 4 per row and pixel disparity) and the diving /
+ * gravity thresholds are rebuilt on the device for the frame; the sky and
+ * object tables do not depend on the pose.  Valid poses: horizon_row a
+ * multiple of 1/256 with |horizon_row| <= 2^20, pitch finite with
+ * cos(pitch) > 0, and a ground disparity at the frame's bottom row of at
+ * most max_disparity. */
+typedef struct {
+    double horizon_row, pitch_rad;
+} stixels_pose;
 
 /* Validate the parameters, build the offline cost tables of Sec. 3.4 on the
  * host in FP64 (Eq. 4 for every pair of pixel disparity and model disparity,
@@ -159,6 +181,17 @@ int stixels_output_bytes(const stixels_handle *h, int32_t width, int32_t height,
  * or the batch API).  Allocates nothing. */
 int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, int32_t height,
                     void *stream, const stixels_output *out);
+
+/* stixels_compute for a frame with its own camera pose (see stixels_pose):
+ * the frame's ground table and thresholds are built on the device into the
+ * handle's pose area, on `stream`, ahead of the frame's kernels.  Same
+ * arguments, ownership and errors as stixels_compute, plus
+ * STIXELS_E_INVALID_ARG for a null or invalid pose and STIXELS_E_RANGE when
+ * the handle's cost range leaves no room for other poses.  pose equal to the
+ * handle's camera gives the results of stixels_compute. */
+int stixels_compute_pose(stixels_handle *h, const float *d_disparity, int32_t width,
+                         int32_t height, const stixels_pose *pose, void *stream,
+                         const stixels_output *out);
 
 /* How stixels_compute runs a frame: 1 = three staged kernels (reduction and
  * transpose, prefix tables into the handle's workspace, recurrence and
@@ -217,16 +250,28 @@ typedef struct {
     const float *d_disparity;    /* device [height][width] */
     int32_t width, height;
     stixels_output out;
+    stixels_pose pose;           /* the frame's own camera pose, read when use_pose = 1 */
+    int32_t use_pose;            /* 0 = the handle's camera, 1 = pose (needs a batch
+                                    created with STIXELS_BATCH_POSES) */
+    int32_t reserved0;
 } stixels_job;
 
 typedef struct {
     int32_t max_jobs;            /* frames per call */
     int32_t max_tasks;           /* (frame, column) pairs per call */
     int32_t max_height;          /* tallest frame */
-    int32_t max_disparity;       /* largest d_range of the handles used */
+    int32_t max_disparity;       /* most disparity bins of the handles used
+                                    (max_disparity << subpixel_log2) */
     int32_t workgroups;          /* persistent workgroups, 0 = chosen by the library */
-    int32_t reserved0;
+    int32_t flags;               /* STIXELS_BATCH_* bits */
 } stixels_batch_config;
+
+/* stixels_batch_config.flags: jobs may bring their own camera pose; the
+ * batch then holds one ground table area per job, max_jobs * (max_height *
+ * max_disparity * 4 + max_height * 8) bytes, filled on the device by a
+ * table-building kernel that runs ahead of the persistent launch (and is
+ * captured with it). */
+#define STIXELS_BATCH_POSES 1
 
 typedef struct stixels_batch stixels_batch;
 
@@ -294,7 +339,8 @@ const char *stixels_batch_last_error(const stixels_batch *b);
 
 /* ------------------------------------------------------------------ debug
  * Host copies of the handle's offline tables (Sec. 3.4), for parity tests.
- * which = STIXELS_TABLE_*; bytes must equal the table's size:
+ * Here and below d_range counts disparity bins (max_disparity <<
+ * subpixel_log2).  which = STIXELS_TABLE_*; bytes must equal the table's size:
  *   SKY    float[d_range]                  cost of sky per pixel disparity
  *   GROUND float[max_height][d_range]      ground cost per top-down image row
  *   OBJECT float[d_range][d_range]         [f][d]: object of mean f, pixel disparity d
@@ -308,6 +354,15 @@ int stixels_debug_table(const stixels_handle *h, int32_t which, void *host_dst, 
  * OBJECT, FG_HI, FG_LO, each laid out as for stixels_debug_table; bytes must
  * equal the sum of their sizes. */
 int stixels_debug_tables(const stixels_handle *h, void *host_dst, size_t bytes);
+
+/* The ground table and thresholds of a frame of this height under `pose`,
+ * built on the device as stixels_compute_pose builds them (synchronises
+ * `stream`): host_dst receives GROUND float[height][d_range] by top-down
+ * row, then FG_HI int32[height] and FG_LO int32[height]; bytes must equal
+ * height * (4 * d_range + 8).  Uses the handle's pose area (not with
+ * STIXELS_FLAG_BATCH_ONLY). */
+int stixels_debug_pose_tables(stixels_handle *h, const stixels_pose *pose, int32_t height,
+                              void *host_dst, size_t bytes, void *stream);
 
 /* The same tables built on the host from `params` alone, without a handle or
  * a device (validation and range checks as in stixels_create; the error

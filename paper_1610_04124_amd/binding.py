@@ -35,7 +35,7 @@ EXPORTS = (
     "stixels_debug_stage", "stixels_selftest_mean", "stixels_output_bytes",
     "stixels_compute_batch", "stixels_debug_tables", "stixels_set_frame_path",
     "stixels_get_frame_path", "stixels_device_bytes", "stixels_batch_device_bytes",
-    "stixels_debug_stage_times",
+    "stixels_debug_stage_times", "stixels_compute_pose", "stixels_debug_pose_tables",
 )
 
 
@@ -66,7 +66,7 @@ class Params(C.Structure):
                 ("max_disparity", C.c_int32), ("max_width", C.c_int32),
                 ("max_height", C.c_int32), ("max_stixels_per_column", C.c_int32),
                 ("reduce_mode", C.c_int32), ("cost_grid_log2", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("subpixel_log2", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class Output(C.Structure):
@@ -74,14 +74,30 @@ class Output(C.Structure):
                 ("overflow", C.c_void_p), ("capacity", C.c_int32), ("reserved0", C.c_int32)]
 
 
+class Pose(C.Structure):
+    _fields_ = [("horizon_row", C.c_double), ("pitch_rad", C.c_double)]
+
+
 class Job(C.Structure):
     _fields_ = [("handle", C.c_void_p), ("d_disparity", C.c_void_p), ("width", C.c_int32),
-                ("height", C.c_int32), ("out", Output)]
+                ("height", C.c_int32), ("out", Output), ("pose", Pose),
+                ("use_pose", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class BatchConfig(C.Structure):
     _fields_ = [("max_jobs", C.c_int32), ("max_tasks", C.c_int32), ("max_height", C.c_int32),
-                ("max_disparity", C.c_int32), ("workgroups", C.c_int32), ("reserved0", C.c_int32)]
+                ("max_disparity", C.c_int32), ("workgroups", C.c_int32), ("flags", C.c_int32)]
+
+
+BATCH_POSES = 1
+
+
+def to_pose(pose) -> Pose:
+    """(horizon_row, pitch_rad), or a dict with those keys, as a stixels_pose."""
+    if isinstance(pose, dict):
+        return Pose(float(pose["horizon_row"]), float(pose.get("pitch_rad", 0.0)))
+    hr, pitch = pose
+    return Pose(float(hr), float(pitch))
 
 
 _lib = None
@@ -106,6 +122,8 @@ def lib():
         L.stixels_num_columns.argtypes = [vp, i32, P(i32)]
         L.stixels_output_capacity.argtypes = [vp, i32, P(i32)]
         L.stixels_compute.argtypes = [vp, vp, i32, i32, vp, P(Output)]
+        L.stixels_compute_pose.argtypes = [vp, vp, i32, i32, P(Pose), vp, P(Output)]
+        L.stixels_debug_pose_tables.argtypes = [vp, P(Pose), i32, vp, C.c_size_t, vp]
         L.stixels_last_error.argtypes = [vp]
         L.stixels_last_error.restype = C.c_char_p
         L.stixels_status_string.argtypes = [C.c_int]
@@ -143,6 +161,14 @@ def lib():
     return _lib
 
 
+def bins(params: dict) -> int:
+    """Disparity bins of a parameter set: max_disparity px in bins of
+    2^-subpixel_log2 px (an out-of-range exponent is left to the library to
+    reject)."""
+    k = int(params.get("subpixel_log2", 0))
+    return int(params["max_disparity"]) << k if 0 <= k <= 8 else int(params["max_disparity"])
+
+
 def to_params(params: dict) -> Params:
     p = Params()
     for k in ("focal_px", "baseline_m", "cam_height_m", "horizon_row", "pitch_rad"):
@@ -161,6 +187,7 @@ def to_params(params: dict) -> Params:
               "max_stixels_per_column", "reduce_mode", "cost_grid_log2"):
         setattr(p, k, int(params[k]))
     p.flags = int(params.get("flags", 0))
+    p.subpixel_log2 = int(params.get("subpixel_log2", 0))
     return p
 
 
@@ -235,7 +262,8 @@ class Stixels:
             raise StixelsError(rc, "stixels_create: " + lib().stixels_last_error(None).decode())
         self.h = h
         self.s = int(params["stixel_width"])
-        self.D = int(params["max_disparity"])
+        # disparity bins: max_disparity px in bins of 2^-subpixel_log2 px
+        self.D = bins(params)
         self.max_height = int(params["max_height"])
 
     def close(self):
@@ -313,8 +341,11 @@ class Stixels:
         dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         return FrameOutput(self.num_columns(width), self.capacity(height), dev)
 
-    def compute(self, disp, out: FrameOutput | None = None, stream=None) -> FrameOutput:
-        """Enqueue the segmentation of one device frame [height, width] float32."""
+    def compute(self, disp, out: FrameOutput | None = None, stream=None,
+                pose=None) -> FrameOutput:
+        """Enqueue the segmentation of one device frame [height, width] float32,
+        with the handle's camera or, given `pose` = (horizon_row, pitch_rad),
+        with that frame's own pose (stixels_compute_pose)."""
         import torch
         _check_device_tensor(disp, torch.float32, "disparity")
         H, W = disp.shape
@@ -322,11 +353,31 @@ class Stixels:
             out = self.new_output(W, H, disp.device)
         self.check_output(out, W, disp.device)
         o = out.struct()
-        rc = lib().stixels_compute(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
-                                   _stream_ptr(stream), C.byref(o))
+        if pose is None:
+            rc = lib().stixels_compute(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
+                                       _stream_ptr(stream), C.byref(o))
+        else:
+            ps = to_pose(pose)
+            rc = lib().stixels_compute_pose(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
+                                            C.byref(ps), _stream_ptr(stream), C.byref(o))
         if rc != OK:
-            self._err(rc, "stixels_compute")
+            self._err(rc, "stixels_compute" if pose is None else "stixels_compute_pose")
         return out
+
+    def debug_pose_tables(self, pose, height: int, stream=None):
+        """The ground table [height][D] and diving / gravity thresholds
+        [height] that the device builds for a frame pose (synchronises)."""
+        H = int(height)
+        buf = np.zeros(H * (4 * self.D + 8), np.uint8)
+        ps = to_pose(pose)
+        rc = lib().stixels_debug_pose_tables(self.h, C.byref(ps), H, buf.ctypes.data, buf.nbytes,
+                                             _stream_ptr(stream))
+        if rc != OK:
+            self._err(rc, "stixels_debug_pose_tables")
+        g = buf[:H * 4 * self.D].view(np.float32).reshape(H, self.D).copy()
+        hi = buf[H * 4 * self.D:H * (4 * self.D + 4)].view(np.int32).copy()
+        lo = buf[H * (4 * self.D + 4):].view(np.int32).copy()
+        return g, hi, lo
 
     def check_output(self, out: FrameOutput, width: int, device) -> None:
         """The kernels write ncols columns of `capacity` records into the
@@ -406,7 +457,7 @@ def _table_shape(which, D, Hm):
 
 def host_table(params: dict, which: int) -> np.ndarray:
     """An offline table built on the host by the library, without a device."""
-    shape, dt = _table_shape(which, int(params["max_disparity"]), int(params["max_height"]))
+    shape, dt = _table_shape(which, bins(params), int(params["max_height"]))
     a = np.zeros(shape, dt)
     p = to_params(params)
     rc = lib().stixels_host_table(C.byref(p), int(which), a.ctypes.data, a.nbytes)
@@ -447,11 +498,12 @@ class Batch:
     sizes and stixel widths); see stixels_batch_* in include/stixels.h."""
 
     def __init__(self, max_jobs: int, max_tasks: int, max_height: int, max_disparity: int,
-                 workgroups: int = 0):
+                 workgroups: int = 0, poses: bool = False):
         cfg = BatchConfig()
         cfg.max_jobs, cfg.max_tasks = int(max_jobs), int(max_tasks)
         cfg.max_height, cfg.max_disparity = int(max_height), int(max_disparity)
         cfg.workgroups = int(workgroups)
+        cfg.flags = BATCH_POSES if poses else 0
         b = C.c_void_p()
         rc = lib().stixels_batch_create(C.byref(cfg), C.byref(b))
         if rc != OK:
@@ -476,11 +528,15 @@ class Batch:
 
     @staticmethod
     def make_jobs(items):
-        """items: sequence of (Stixels, device frame tensor [H, W], FrameOutput)."""
+        """items: sequence of (Stixels, device frame tensor [H, W], FrameOutput)
+        or (Stixels, frame, FrameOutput, pose) with pose = (horizon_row,
+        pitch_rad) for a frame with its own camera pose (None = the handle's)."""
         import torch
         arr = (Job * len(items))()
         keep = []
-        for i, (h, disp, out) in enumerate(items):
+        for i, item in enumerate(items):
+            h, disp, out = item[:3]
+            pose = item[3] if len(item) > 3 else None
             _check_device_tensor(disp, torch.float32, "disparity")
             H, W = disp.shape
             h.check_output(out, W, disp.device)
@@ -488,6 +544,9 @@ class Batch:
             arr[i].d_disparity = disp.data_ptr()
             arr[i].width, arr[i].height = int(W), int(H)
             arr[i].out = out.struct()
+            if pose is not None:
+                arr[i].pose = to_pose(pose)
+                arr[i].use_pose = 1
             keep.append((h, disp, out))
         return arr, keep
 

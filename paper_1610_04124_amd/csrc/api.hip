@@ -84,8 +84,11 @@ int validate(const stixels_params* p, std::string& why) {
     if (p->reduce_mode != 0 && p->reduce_mode != 1) return bad("reduce_mode must be 0 or 1");
     if (p->cost_grid_log2 < 0 || p->cost_grid_log2 > 12) return bad("cost_grid_log2 must lie in 0..12");
     if (p->flags & ~STIXELS_FLAG_BATCH_ONLY) return bad("unknown bits in flags");
-    if ((long long)p->max_height * p->max_disparity > (1LL << 20)) {
-        why = "max_height * max_disparity must not exceed 2^20 (rounded-mean division bound)";
+    if (p->subpixel_log2 < 0 || p->subpixel_log2 > 3) return bad("subpixel_log2 must lie in 0..3");
+    if ((p->max_disparity << p->subpixel_log2) > kMaxDisparity)
+        return bad("max_disparity * 2^subpixel_log2 (disparity bins) must not exceed 256");
+    if ((long long)p->max_height * (p->max_disparity << p->subpixel_log2) > (1LL << 20)) {
+        why = "max_height * disparity bins must not exceed 2^20 (rounded-mean division bound)";
         return STIXELS_E_RANGE;
     }
     return STIXELS_OK;
@@ -111,14 +114,21 @@ void release(stixels_handle* h) {
     (void)hipFree(h->d_prefix);
     (void)hipFree(h->d_range);
     (void)hipFree(h->d_po);
+    (void)hipFree(h->d_pose_ground);
+    (void)hipFree(h->d_pose_hi);
+    (void)hipFree(h->d_pose_lo);
 }
 
 // Offline tables (Sec. 3.4) in FP64, rounded to the grid and stored as FP32.
 int build_tables(stixels_handle* h) {
     const stixels_params& p = h->p;
     const stixels_model& m = p.model;
-    const int D = h->D, Hmax = h->Hmax, g = p.cost_grid_log2;
-    const double dr = (double)D;
+    // D disparity bins of 2^-k px (k = subpixel_log2); Eq. 4 is evaluated at
+    // the bins' disparities in px, the outlier density stays uniform over
+    // [0, max_disparity] px
+    const int D = h->D, Hmax = h->Hmax, g = p.cost_grid_log2, k = p.subpixel_log2;
+    const double dr = (double)p.max_disparity;
+    auto px = [k](int i) { return std::ldexp((double)i, -k); };
     const double hr = p.camera.horizon_row;
     const double alpha = p.camera.baseline_m * std::cos(p.camera.pitch_rad) / p.camera.cam_height_m;
     double cmax = 0.0;
@@ -128,7 +138,7 @@ int build_tables(stixels_handle* h) {
     };
     h->sky.resize(D);
     for (int d = 0; d < D; ++d)
-        h->sky[d] = keep(to_grid(pixel_cost(d, 0.0, m.sigma_sky, m.p_out, dr), g));
+        h->sky[d] = keep(to_grid(pixel_cost(px(d), 0.0, m.sigma_sky, m.p_out, dr), g));
     // ground rows by top-down image row r: model disparity alpha (r - horizon),
     // zero (never used) above the horizon
     h->ground.assign((size_t)Hmax * D, 0.0f);
@@ -140,19 +150,20 @@ int build_tables(stixels_handle* h) {
             const double e = m.ground_slope_noise * mu;
             const double sg = std::sqrt(m.sigma_disp * m.sigma_disp + e * e);
             for (int d = 0; d < D; ++d)
-                h->ground[(size_t)r * D + d] = keep(to_grid(pixel_cost(d, mu, sg, m.p_out, dr), g));
+                h->ground[(size_t)r * D + d] = keep(to_grid(pixel_cost(px(d), mu, sg, m.p_out, dr), g));
         }
-        h->fg_hi[r] = (int32_t)std::floor(mu + m.diving_tol_px);
-        h->fg_lo[r] = (int32_t)std::ceil(mu - m.gravity_tol_px);
+        // thresholds in bins
+        h->fg_hi[r] = (int32_t)std::floor(std::ldexp(mu + m.diving_tol_px, k));
+        h->fg_lo[r] = (int32_t)std::ceil(std::ldexp(mu - m.gravity_tol_px, k));
     }
     // object table stored as [f][d]: one row per model mean f
     h->object_t.resize((size_t)D * D);
     for (int f = 0; f < D; ++f) {
-        const double e = (double)f * (double)f * m.object_depth_extent_m /
+        const double e = px(f) * px(f) * m.object_depth_extent_m /
                          (p.camera.focal_px * p.camera.baseline_m);
         const double so = std::sqrt(m.sigma_disp * m.sigma_disp + e * e);
         for (int d = 0; d < D; ++d)
-            h->object_t[(size_t)f * D + d] = keep(to_grid(pixel_cost(d, f, so, m.p_out, dr), g));
+            h->object_t[(size_t)f * D + d] = keep(to_grid(pixel_cost(px(d), px(f), so, m.p_out, dr), g));
     }
     h->object_df.resize((size_t)D * D);
     for (int f = 0; f < D; ++f)
@@ -173,12 +184,20 @@ int build_tables(stixels_handle* h) {
     h->prior.c_ord = (float)to_grid(m.ordering_cost, g);
     h->prior.c_grav = (float)to_grid(m.gravity_cost, g);
     h->prior.c_dive = (float)to_grid(m.diving_cost, g);
-    h->prior.tau_ord = m.ordering_tol_px;
+    h->prior.tau_ord = m.ordering_tol_px << k;     // in bins
     h->prior.mean_eps = (float)std::ldexp((double)D, -22);
     // exactness: every prefix, cost and intermediate of the recurrence is a
     // multiple of 2^-g bounded by 2 (h+1) cmax plus the priors
     const double bound = 2.0 * (Hmax + 1) * cmax + fmaxp + tmaxp + h->prior.c_ord +
                          h->prior.c_grav + h->prior.c_dive;
+    // a frame pose (stixels_compute_pose) keeps every ground model disparity
+    // in [0, d_range]; its ground costs then lie between the object cost of
+    // pixel 0 at mean 0 (the smallest Gaussian cost any such model reaches)
+    // and the outlier cost
+    const double c_out = std::log(dr) - std::log(m.p_out);
+    const double pose_bound = 2.0 * (Hmax + 1) * std::fmax(cmax, c_out) + fmaxp + tmaxp +
+                              h->prior.c_ord + h->prior.c_grav + h->prior.c_dive;
+    h->pose_in_range = pose_bound < std::ldexp(1.0, 24 - g);
     if (!(bound < std::ldexp(1.0, 24 - g))) {
         char buf[200];
         snprintf(buf, sizeof buf,
@@ -210,7 +229,7 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     stixels_handle* h = new (std::nothrow) stixels_handle;
     if (!h) return STIXELS_E_NOMEM;
     h->p = *params;
-    h->D = params->max_disparity;
+    h->D = params->max_disparity << params->subpixel_log2;   // disparity bins
     h->Hmax = params->max_height;
     h->Wmax = params->max_width;
     h->s = params->stixel_width;
@@ -242,7 +261,11 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
         bool ok = hipMalloc(reinterpret_cast<void**>(&h->d_q), nc * h->Hmax * sizeof(int16_t)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_prefix), 4 * nc * H1 * sizeof(float)) == hipSuccess &&
                   hipMalloc(reinterpret_cast<void**>(&h->d_range), 2 * nc * sizeof(int32_t)) == hipSuccess &&
-                  hipMalloc(reinterpret_cast<void**>(&h->d_po), h->ws_bytes) == hipSuccess;
+                  hipMalloc(reinterpret_cast<void**>(&h->d_po), h->ws_bytes) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_pose_ground),
+                            (size_t)h->Hmax * h->D * sizeof(float)) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_pose_hi), (size_t)h->Hmax * sizeof(int32_t)) == hipSuccess &&
+                  hipMalloc(reinterpret_cast<void**>(&h->d_pose_lo), (size_t)h->Hmax * sizeof(int32_t)) == hipSuccess;
         if (!ok) rc = fail(h, STIXELS_E_NOMEM, "hipMalloc of the frame workspace failed");
     }
     if (rc != STIXELS_OK) {
@@ -270,7 +293,8 @@ int stixels_device_bytes(const stixels_handle* h, size_t* bytes) {
     if (h->d_po) {
         const size_t nc = (size_t)h->ncols_max, H1 = (size_t)h->Hmax + 1;
         n += nc * h->Hmax * sizeof(int16_t) + 4 * nc * H1 * sizeof(float) +
-             2 * nc * sizeof(int32_t) + h->ws_bytes;
+             2 * nc * sizeof(int32_t) + h->ws_bytes +
+             (size_t)h->Hmax * (h->D * sizeof(float) + 2 * sizeof(int32_t));
     }
     size_t b = 0;
     if (h->auto_batch && stixels_batch_device_bytes(h->auto_batch, &b) == STIXELS_OK) n += b;
@@ -290,8 +314,15 @@ int stixels_output_capacity(const stixels_handle* h, int32_t height, int32_t* ca
     return STIXELS_OK;
 }
 
-int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, int32_t height,
-                    void* stream, const stixels_output* out) {
+}  // extern "C"
+
+namespace {
+
+// A frame through the path of stixels_compute, with the handle's camera
+// (pose == nullptr) or with the frame's own pose, whose ground table is built
+// on the device first.
+int compute_frame(stixels_handle* h, const float* d_disparity, int32_t width, int32_t height,
+                  const stixels_pose* pose, void* stream, const stixels_output* out) {
     if (!h) return STIXELS_E_INVALID_ARG;
     if (!d_disparity || !out || !out->counts || !out->records || !out->total_cost ||
         !out->overflow)
@@ -304,12 +335,34 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
     if (!h->d_po)
         return fail(h, STIXELS_E_INVALID_ARG, "handle created for the batch API only (no workspace)");
     const hipStream_t st = static_cast<hipStream_t>(stream);
+    DeviceModel m = device_model(h);
+    if (pose) {
+        if (!h->pose_in_range)
+            return fail(h, STIXELS_E_RANGE,
+                        "the handle's cost range leaves no room for frame poses (exact grid)");
+        PoseItem it{};
+        const char* why = "";
+        const int rc = make_pose_item(h->p, h->D, *pose, height, h->d_pose_ground, h->d_pose_hi,
+                                      h->d_pose_lo, &it, &why);
+        if (rc != STIXELS_OK) return fail(h, rc, why);
+        const hipError_t e = launch_pose_tables(it, st);
+        if (e != hipSuccess)
+            return fail(h, STIXELS_E_HIP, std::string("pose table launch failed: ") + hipGetErrorString(e));
+        m.ground = h->d_pose_ground;
+        m.fg_hi = h->d_pose_hi;
+        m.fg_lo = h->d_pose_lo;
+        m.horizon_row = pose->horizon_row;
+    }
     const int waves = frame_waves(h->waves, height, width / h->s, h->num_cu);
     if (frame_path_of(h) == 2) {
         int grid = 0;
-        const hipError_t e = persist::launch_frame_fused(
-            persist::make_job_desc(h, d_disparity, width, height, *out), h->d_po, h->ws_bytes,
-            waves, h->num_cu, st, &grid);
+        persist::JobDesc job = persist::make_job_desc(h, d_disparity, width, height, *out);
+        job.ground = m.ground;
+        job.fg_hi = m.fg_hi;
+        job.fg_lo = m.fg_lo;
+        job.vtop = ground_top(m.horizon_row, height);
+        const hipError_t e = persist::launch_frame_fused(job, h->d_po, h->ws_bytes, waves,
+                                                         h->num_cu, st, &grid);
         if (e != hipSuccess)
             return fail(h, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
         h->last_W = width;
@@ -318,8 +371,7 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
         return STIXELS_OK;
     }
     const int ncols = width / h->s;
-    const int vtop = ground_top(h->p.camera.horizon_row, height);
-    DeviceModel m = device_model(h);
+    const int vtop = ground_top(m.horizon_row, height);
     FrameWorkspace ws{h->d_q, h->d_prefix, h->d_range, h->d_po};
     FrameOutput fo{out->counts, reinterpret_cast<uint32_t*>(out->records), out->total_cost,
                    out->overflow, out->capacity};
@@ -333,6 +385,50 @@ int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, 
     h->last_W = width;
     h->last_H = height;
     h->last_path = 1;
+    return STIXELS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stixels_compute(stixels_handle* h, const float* d_disparity, int32_t width, int32_t height,
+                    void* stream, const stixels_output* out) {
+    return compute_frame(h, d_disparity, width, height, nullptr, stream, out);
+}
+
+int stixels_compute_pose(stixels_handle* h, const float* d_disparity, int32_t width,
+                         int32_t height, const stixels_pose* pose, void* stream,
+                         const stixels_output* out) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (!pose) return fail(h, STIXELS_E_INVALID_ARG, "null pose");
+    return compute_frame(h, d_disparity, width, height, pose, stream, out);
+}
+
+int stixels_debug_pose_tables(stixels_handle* h, const stixels_pose* pose, int32_t height,
+                              void* host_dst, size_t bytes, void* stream) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (!pose || !host_dst || height < 1 || height > h->Hmax || !h->d_pose_ground)
+        return fail(h, STIXELS_E_INVALID_ARG, "null pose or buffer, height out of range or batch-only handle");
+    const size_t gbytes = (size_t)height * h->D * sizeof(float);
+    const size_t tbytes = (size_t)height * sizeof(int32_t);
+    if (bytes != gbytes + 2 * tbytes)
+        return fail(h, STIXELS_E_INVALID_ARG, "bytes must equal height * (4 d_range + 8)");
+    PoseItem it{};
+    const char* why = "";
+    const int rc = make_pose_item(h->p, h->D, *pose, height, h->d_pose_ground, h->d_pose_hi,
+                                  h->d_pose_lo, &it, &why);
+    if (rc != STIXELS_OK) return fail(h, rc, why);
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    char* dst = static_cast<char*>(host_dst);
+    hipError_t e = launch_pose_tables(it, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(dst, h->d_pose_ground, gbytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(dst + gbytes, h->d_pose_hi, tbytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(dst + gbytes + tbytes, h->d_pose_lo, tbytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return fail(h, STIXELS_E_HIP, std::string("pose tables failed: ") + hipGetErrorString(e));
     return STIXELS_OK;
 }
 
@@ -483,7 +579,7 @@ int stixels_host_table(const stixels_params* params, int32_t which, void* host_d
     }
     stixels_handle h;
     h.p = *params;
-    h.D = params->max_disparity;
+    h.D = params->max_disparity << params->subpixel_log2;
     h.Hmax = params->max_height;
     h.Wmax = params->max_width;
     h.s = params->stixel_width;

@@ -61,6 +61,14 @@ struct stixels_batch {
     size_t scratch_floats = 0;
     JobDesc* h_jobs = nullptr;   // pinned staging
     int2* h_tasks = nullptr;
+    // frames with their own pose (STIXELS_BATCH_POSES): one ground table
+    // area per job slot, and the table builds of the eager path and the graph
+    char* d_pose_area = nullptr;
+    size_t pose_area_bytes = 0;  // per job slot
+    PoseItem* d_pose_items = nullptr;
+    PoseItem* d_pose_items_g = nullptr;
+    PoseItem* h_pose_items = nullptr;
+    int npose = 0, pose_hmax = 0;
     hipEvent_t staged = nullptr;
     bool staged_pending = false;
     hipGraph_t graph = nullptr;
@@ -131,9 +139,34 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int c) { return jobs[a].height > jobs[c].height; });
     int t = 0;
-    for (int i = 0; i < n; ++i)
-        b->h_jobs[i] = make_job_desc(jobs[i].handle, jobs[i].d_disparity, jobs[i].width,
-                                     jobs[i].height, jobs[i].out);
+    b->npose = 0;
+    b->pose_hmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const stixels_job& j = jobs[i];
+        b->h_jobs[i] = make_job_desc(j.handle, j.d_disparity, j.width, j.height, j.out);
+        if (!j.use_pose) continue;
+        if (!b->d_pose_area)
+            return bfail(b, STIXELS_E_INVALID_ARG, "job " + std::to_string(i) +
+                                                       " has a pose: create the batch with STIXELS_BATCH_POSES");
+        if (!j.handle->pose_in_range)
+            return bfail(b, STIXELS_E_RANGE, "job " + std::to_string(i) +
+                                                 ": its handle's cost range leaves no room for poses");
+        char* area = b->d_pose_area + (size_t)i * b->pose_area_bytes;
+        float* G = reinterpret_cast<float*>(area);
+        int32_t* hi = reinterpret_cast<int32_t*>(
+            area + (size_t)b->cfg.max_height * b->cfg.max_disparity * sizeof(float));
+        int32_t* lo = hi + b->cfg.max_height;
+        const char* why = "";
+        const int rc = make_pose_item(j.handle->p, j.handle->D, j.pose, j.height, G, hi, lo,
+                                      &b->h_pose_items[b->npose], &why);
+        if (rc != STIXELS_OK) return bfail(b, rc, "job " + std::to_string(i) + ": " + why);
+        ++b->npose;
+        b->pose_hmax = std::max(b->pose_hmax, (int)j.height);
+        b->h_jobs[i].ground = G;
+        b->h_jobs[i].fg_hi = hi;
+        b->h_jobs[i].fg_lo = lo;
+        b->h_jobs[i].vtop = ground_top(j.pose.horizon_row, j.height);
+    }
     // two columns per wave only where that kernel exists (h <= 512,
     // d_range <= 128); a task is then a (frame, even column) pair
     const bool pairs = want_pairs && kernel_slots(hmax) <= 8 && kernel_chunks(dmax) == 2;
@@ -175,11 +208,14 @@ int choose_grid(stixels_batch* b, int slots, int nch, int waves, bool pairs, lon
     return STIXELS_OK;
 }
 
-int upload(stixels_batch* b, JobDesc* dj, int2* dt, int n, int ntasks, hipStream_t st) {
+int upload(stixels_batch* b, JobDesc* dj, int2* dt, PoseItem* dp, int n, int ntasks,
+           hipStream_t st) {
     if (hipMemcpyAsync(dj, b->h_jobs, sizeof(JobDesc) * n, hipMemcpyHostToDevice, st) !=
             hipSuccess ||
         hipMemcpyAsync(dt, b->h_tasks, sizeof(int2) * ntasks, hipMemcpyHostToDevice, st) !=
-            hipSuccess)
+            hipSuccess ||
+        (b->npose > 0 && hipMemcpyAsync(dp, b->h_pose_items, sizeof(PoseItem) * b->npose,
+                                        hipMemcpyHostToDevice, st) != hipSuccess))
         return bfail(b, STIXELS_E_HIP, "descriptor upload failed");
     if (hipEventRecord(b->staged, st) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "event record failed");
@@ -203,7 +239,8 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
     *out = nullptr;
     if (cfg->max_jobs < 1 || cfg->max_tasks < 1 || cfg->max_height < 1 ||
         cfg->max_height > kMaxHeight || cfg->max_disparity < 2 ||
-        cfg->max_disparity > kMaxDisparity || cfg->workgroups < 0)
+        cfg->max_disparity > kMaxDisparity || cfg->workgroups < 0 ||
+        (cfg->flags & ~STIXELS_BATCH_POSES))
         return STIXELS_E_INVALID_ARG;
     stixels_batch* b = new (std::nothrow) stixels_batch;
     if (!b) return STIXELS_E_NOMEM;
@@ -245,6 +282,18 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
             hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
         if (!ok) rc = STIXELS_E_NOMEM;
     }
+    if (rc == STIXELS_OK && (cfg->flags & STIXELS_BATCH_POSES)) {
+        b->pose_area_bytes = (size_t)cfg->max_height *
+                             ((size_t)cfg->max_disparity * sizeof(float) + 2 * sizeof(int32_t));
+        const bool ok =
+            hipMalloc(reinterpret_cast<void**>(&b->d_pose_area),
+                      b->pose_area_bytes * (size_t)cfg->max_jobs) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_pose_items), sizeof(PoseItem) * cfg->max_jobs) == hipSuccess &&
+            hipMalloc(reinterpret_cast<void**>(&b->d_pose_items_g), sizeof(PoseItem) * cfg->max_jobs) == hipSuccess &&
+            hipHostMalloc(reinterpret_cast<void**>(&b->h_pose_items), sizeof(PoseItem) * cfg->max_jobs,
+                          hipHostMallocDefault) == hipSuccess;
+        if (!ok) rc = STIXELS_E_NOMEM;
+    }
     if (rc != STIXELS_OK) {
         stixels_batch_destroy(b);
         return rc;
@@ -264,6 +313,10 @@ int stixels_batch_destroy(stixels_batch* b) {
     (void)hipFree(b->d_tasks_g);
     (void)hipFree(b->d_counter_g);
     (void)hipFree(b->d_scratch);
+    (void)hipFree(b->d_pose_area);
+    (void)hipFree(b->d_pose_items);
+    (void)hipFree(b->d_pose_items_g);
+    if (b->h_pose_items) (void)hipHostFree(b->h_pose_items);
     if (b->h_jobs) (void)hipHostFree(b->h_jobs);
     if (b->h_tasks) (void)hipHostFree(b->h_tasks);
     if (b->staged) (void)hipEventDestroy(b->staged);
@@ -281,10 +334,11 @@ int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, pairs, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
-    rc = upload(b, b->d_jobs, b->d_tasks, n, ntasks, st);
+    rc = upload(b, b->d_jobs, b->d_tasks, b->d_pose_items, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
-    const hipError_t e =
-        pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
+    hipError_t e = launch_pose_tables(b->d_pose_items, b->npose, b->pose_hmax, st);
+    if (e == hipSuccess)
+        e = pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
                                   b->d_counter, b->d_scratch, stride, hmax)
               : launch_batch(slots, nch, waves, grid, st, b->d_jobs, b->d_tasks, ntasks,
                              b->d_counter, b->d_scratch, stride, hmax);
@@ -310,7 +364,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
     // the graph reads its own descriptor copy, uploaded once here
-    rc = upload(b, b->d_jobs_g, b->d_tasks_g, n, ntasks, st);
+    rc = upload(b, b->d_jobs_g, b->d_tasks_g, b->d_pose_items_g, n, ntasks, st);
     if (rc != STIXELS_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "synchronising the capture stream failed");
@@ -318,8 +372,9 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     destroy_graph(b);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, STIXELS_E_HIP, "hipStreamBeginCapture failed");
-    const hipError_t e =
-        pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+    hipError_t e = launch_pose_tables(b->d_pose_items_g, b->npose, b->pose_hmax, st);
+    if (e == hipSuccess)
+        e = pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
                                   b->d_counter_g, b->d_scratch, stride, hmax)
               : launch_batch(slots, nch, waves, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
                              b->d_counter_g, b->d_scratch, stride, hmax);
@@ -378,6 +433,8 @@ int stixels_batch_device_bytes(const stixels_batch* b, size_t* bytes) {
     *bytes = 2 * (sizeof(JobDesc) * (size_t)b->cfg.max_jobs +
                   sizeof(int2) * (size_t)b->cfg.max_tasks + sizeof(unsigned int)) +
              sizeof(float) * b->scratch_floats + kTableGuardBytes;
+    if (b->d_pose_area)
+        *bytes += (b->pose_area_bytes + 2 * sizeof(PoseItem)) * (size_t)b->cfg.max_jobs;
     return STIXELS_OK;
 }
 
@@ -393,7 +450,9 @@ int stixels_compute_batch(const stixels_job* jobs, int32_t n, void* stream) {
     stixels_handle* owner = jobs[0].handle;
     int hmax = 1, dmax = 2;
     long long tasks = 0;
+    bool poses = false;
     for (int i = 0; i < n; ++i) {
+        poses = poses || jobs[i].use_pose;
         const stixels_handle* h = jobs[i].handle;
         if (!h || jobs[i].width < h->s || jobs[i].height < 1 || jobs[i].height > h->Hmax) {
             owner->err = "job " + std::to_string(i) + ": null handle or size outside its limits";
@@ -409,13 +468,14 @@ int stixels_compute_batch(const stixels_job* jobs, int32_t n, void* stream) {
     }
     stixels_batch* b = owner->auto_batch;
     if (!b || b->cfg.max_jobs < n || b->cfg.max_tasks < tasks || b->cfg.max_height < hmax ||
-        b->cfg.max_disparity < dmax) {
+        b->cfg.max_disparity < dmax || (poses && !(b->cfg.flags & STIXELS_BATCH_POSES))) {
         // grow: the new limits cover this call and every earlier one
         stixels_batch_config c{};
         c.max_jobs = b ? std::max((int)n, (int)b->cfg.max_jobs) : n;
         c.max_tasks = (int)(b ? std::max<long long>(tasks, b->cfg.max_tasks) : tasks);
         c.max_height = b ? std::max(hmax, (int)b->cfg.max_height) : hmax;
         c.max_disparity = b ? std::max(dmax, (int)b->cfg.max_disparity) : dmax;
+        c.flags = (poses || (b && (b->cfg.flags & STIXELS_BATCH_POSES))) ? STIXELS_BATCH_POSES : 0;
         if (b) {
             // earlier launches may still read the old batch's buffers
             if (hipDeviceSynchronize() != hipSuccess) {

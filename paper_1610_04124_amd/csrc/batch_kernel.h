@@ -38,12 +38,13 @@ struct JobDesc {
     float* total;
     uint8_t* overflow;
     int W, H, s, ncols, D, vtop, reduce_mode, cap;
+    int sub;              // disparity bins of 2^-sub px
     Prior prior;
 };
 
-__device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D) {
+__device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D, int sub) {
     switch (s) {
-#define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D);
+#define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D, sub);
         STX_CASE(1) STX_CASE(2) STX_CASE(3) STX_CASE(4) STX_CASE(5) STX_CASE(6) STX_CASE(7)
         STX_CASE(8) STX_CASE(9) STX_CASE(10) STX_CASE(11) STX_CASE(12) STX_CASE(13)
         STX_CASE(14) STX_CASE(15) STX_CASE(16)
@@ -123,7 +124,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         for (int v = threadIdx.x; v < H; v += 64 * W) {
             const int r = H - 1 - v;
             const int x = reduce_any(J.disp + (size_t)r * J.W + (size_t)col * J.s, J.s,
-                                     J.reduce_mode, D);
+                                     J.reduce_mode, D, J.sub);
             qs[v] = (int16_t)x;
             if (x >= 0) {
                 lmin = min(lmin, x);
@@ -305,7 +306,7 @@ __device__ void column_tables(const JobDesc& J, const int col, const bool exists
         int x = -1;
         if (exists && v < H)
             x = reduce_any(J.disp + (size_t)(H - 1 - v) * J.W + (size_t)col * J.s, J.s,
-                           J.reduce_mode, D);
+                           J.reduce_mode, D, J.sub);
         qs[v] = (int16_t)x;
         if (x >= 0) {
             lmin = min(lmin, x);

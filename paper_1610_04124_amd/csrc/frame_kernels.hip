@@ -23,7 +23,7 @@ namespace stx {
 // workgroups to spread one frame over the chip).
 template <int S>
 __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ disp, int W, int H,
-                                                     int ncols, int D, int mode,
+                                                     int ncols, int D, int mode, int sub,
                                                      int16_t* __restrict__ q) {
     __shared__ int16_t tile[64][17];
     const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 16;
@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ d
         const int r = r0 + rl;
         int v = -1;
         if (col < ncols && r < H)
-            v = reduce_strip<S>(disp + (size_t)r * W + (size_t)col * S, mode, D);
+            v = reduce_strip<S>(disp + (size_t)r * W + (size_t)col * S, mode, D, sub);
         tile[tx][rl] = (int16_t)v;
     }
     __syncthreads();
@@ -218,7 +218,7 @@ template <int S>
 static void reduce_launch(dim3 g, const DeviceModel& m, const float* disp, int W, int H, int ncols,
                           int16_t* q, hipStream_t st) {
     hipLaunchKernelGGL(reduce_kernel<S>, g, dim3(256), 0, st, disp, W, H, ncols, m.D,
-                       m.reduce_mode, q);
+                       m.reduce_mode, m.sub, q);
 }
 
 hipError_t launch_reduce(const DeviceModel& m, const float* disp, int W, int H, int ncols,

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "launch.h"
+#include "pose.h"
 #include "stixels.h"
 
 struct stixels_handle {
@@ -35,6 +36,11 @@ struct stixels_handle {
     float* d_prefix = nullptr;
     int32_t* d_range = nullptr;
     float* d_po = nullptr;
+    // the ground table and thresholds of the last frame with its own pose
+    float* d_pose_ground = nullptr;    // [Hmax][D]
+    int32_t* d_pose_hi = nullptr;      // [Hmax]
+    int32_t* d_pose_lo = nullptr;      // [Hmax]
+    bool pose_in_range = false;        // every valid pose keeps the grid arithmetic exact
     stx::Prior prior{};
     std::string err;
     int last_W = 0, last_H = 0;
@@ -43,6 +49,7 @@ struct stixels_handle {
 // Device view of a handle's resident tables and priors.
 inline stx::DeviceModel device_model(const stixels_handle* h) {
     return stx::DeviceModel{h->d_sky, h->d_ground, h->d_object_t, h->d_object_df, h->d_fg_hi,
-                            h->d_fg_lo, h->D, h->Hmax, h->p.reduce_mode, h->s,
+                            h->d_fg_lo, h->D, h->Hmax, h->p.reduce_mode,
+                            h->p.subpixel_log2, h->s,
                             h->p.camera.horizon_row, h->prior};
 }

@@ -70,6 +70,7 @@ struct FrameGeom {
     int W, H, s, ncols, D;
     int vtop;             // highest bottom-up row a ground stixel may reach
     int reduce_mode;
+    int sub;              // disparity bins of 2^-sub px
 };
 
 __device__ __forceinline__ float inf_f() { return __builtin_inff(); }
@@ -87,11 +88,13 @@ __device__ __forceinline__ float writelane_f(float x, int lane, float v) {
 
 // ------------------------------------------------------------------ Sec. 4.1
 // One reduced pixel from the s disparities of a row strip: lower median (mode
-// 0) or FP64 mean (mode 1) of the valid values, rounded half to even and
-// clamped to d_range-1; -1 when no value is valid.  The median is an exact
-// rank selection: the value whose rank (ties broken by position) is (n-1)/2.
+// 0) or FP64 mean (mode 1) of the valid values, in bins of 2^-sub px
+// (scaled by 2^sub, exact), rounded half to even and clamped to the last
+// bin D-1; -1 when no value is valid.  The median is an exact rank
+// selection: the value whose rank (ties broken by position) is (n-1)/2.
 template <int S>
-__device__ __forceinline__ int reduce_strip(const float* __restrict__ p, int mode, int D) {
+__device__ __forceinline__ int reduce_strip(const float* __restrict__ p, int mode, int D,
+                                            int sub) {
     float x[S];
     bool ok[S];
     int n = 0;
@@ -115,7 +118,7 @@ __device__ __forceinline__ int reduce_strip(const float* __restrict__ p, int mod
             }
             if (ok[i] && rank == want) med = x[i];
         }
-        const float r = __builtin_rintf(med);
+        const float r = __builtin_rintf(__builtin_ldexpf(med, sub));
         const float top = (float)(D - 1);
         return (int)(r < top ? r : top);
     }
@@ -123,7 +126,7 @@ __device__ __forceinline__ int reduce_strip(const float* __restrict__ p, int mod
 #pragma unroll
     for (int t = 0; t < S; ++t)
         if (ok[t]) sum += (double)x[t];
-    const double r = __builtin_rint(sum / (double)n);
+    const double r = __builtin_rint(__builtin_ldexp(sum / (double)n, sub));
     const double top = (double)(D - 1);
     return (int)(r < top ? r : top);
 }

@@ -30,6 +30,7 @@ inline JobDesc make_job_desc(const stixels_handle* h, const float* disp, int W, 
     d.D = h->D;
     d.vtop = ground_top(h->p.camera.horizon_row, H);
     d.reduce_mode = h->p.reduce_mode;
+    d.sub = h->p.subpixel_log2;
     d.cap = out.capacity;
     d.prior = h->prior;
     return d;

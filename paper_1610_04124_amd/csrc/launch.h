@@ -19,6 +19,7 @@ struct DeviceModel {
     int D;
     int max_height;
     int reduce_mode;
+    int sub;                // disparity bins of 2^-sub px
     int s;
     double horizon_row;
     Prior prior;

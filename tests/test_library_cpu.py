@@ -59,6 +59,8 @@ def test_struct_layout_matches_header(tmp_path):
 @pytest.mark.parametrize("kw", [
     dict(), dict(max_disparity=256, max_height=880, max_width=2048, stixel_width=3),
     dict(max_disparity=64, max_height=100), dict(cost_grid_log2=6),
+    dict(subpixel_log2=1), dict(max_disparity=64, subpixel_log2=2),
+    dict(max_disparity=32, subpixel_log2=3, reduce_mode=1),
 ])
 def test_host_tables_equal_oracle(kw):
     cam = synth.camera_for_size(kw.get("max_width", 1024), kw.get("max_height", 440))
@@ -172,3 +174,17 @@ def test_create_and_batch_reject_bad_arguments_without_a_device():
     assert L.stixels_selftest_mean(1, 10, None) == B.E_INVALID_ARG
     n = C.c_int64()
     assert L.stixels_selftest_mean(256, 8192, C.byref(n)) == B.E_INVALID_ARG
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(subpixel_log2=2), B.E_INVALID_ARG),            # 512 bins
+    (dict(subpixel_log2=4, max_disparity=16), B.E_INVALID_ARG),
+    (dict(subpixel_log2=-1), B.E_INVALID_ARG),
+])
+def test_subpixel_limits(kw, code):
+    """Disparity bins (max_disparity << subpixel_log2) are limited to 256 and
+    the exponent to 0..3."""
+    p = synth.make_params(camera=synth.CAMERA_1024x440, **kw)
+    with pytest.raises(B.StixelsError) as e:
+        P.host_table(p, B.TABLE_SKY)
+    assert e.value.code == code
