@@ -83,7 +83,13 @@ typedef struct {
     int32_t max_height;          /* largest frame height, 1..1024 */
     int32_t max_stixels_per_column; /* output records per column, 0 = the frame height */
     int32_t reduce_mode;         /* 0 = lower median of the valid pixels, 1 = mean (Sec. 4.1) */
-    int32_t cost_grid_log2;      /* g: costs are multiples of 2^-g nats, 0..12 */
+    int32_t cost_grid_log2;      /* g: costs are multiples of 2^-g nats, 0..12; results then
+                                    equal an FP64 evaluation bit for bit.  -1: costs off
+                                    any grid (FP32 tables and sums, not exact): frames run
+                                    the fused kernel with a stored index table (Sec. 3.3)
+                                    for the backtracking, stixel costs are summed directly
+                                    over their pixels, and results agree with FP64 up to
+                                    near-ties and rounding */
     int32_t flags;               /* STIXELS_FLAG_* bits, 0 = none */
     int32_t subpixel_log2;       /* k, 0..3: disparities in bins of 2^-k px (Sec. 3.4 rounds
                                     pixels and object means to whole px; k > 0 resolves them

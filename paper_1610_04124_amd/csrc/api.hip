@@ -38,8 +38,9 @@ double pixel_cost(double d, double mu, double sigma, double p_out, double d_rang
     return g < c_out ? g : c_out;
 }
 
+// Rounding onto the 2^-g cost grid; g < 0 keeps the value (costs off the grid).
 double to_grid(double x, int g) {
-    if (!std::isfinite(x)) return x;
+    if (g < 0 || !std::isfinite(x)) return x;
     return std::ldexp(std::rint(std::ldexp(x, g)), -g);
 }
 
@@ -82,7 +83,8 @@ int validate(const stixels_params* p, std::string& why) {
     if (p->max_width < p->stixel_width) return bad("max_width must be >= stixel_width");
     if (p->max_stixels_per_column < 0) return bad("max_stixels_per_column must be >= 0");
     if (p->reduce_mode != 0 && p->reduce_mode != 1) return bad("reduce_mode must be 0 or 1");
-    if (p->cost_grid_log2 < 0 || p->cost_grid_log2 > 12) return bad("cost_grid_log2 must lie in 0..12");
+    if (p->cost_grid_log2 < -1 || p->cost_grid_log2 > 12)
+        return bad("cost_grid_log2 must lie in 0..12, or be -1 (costs off the grid)");
     if (p->flags & ~STIXELS_FLAG_BATCH_ONLY) return bad("unknown bits in flags");
     if (p->subpixel_log2 < 0 || p->subpixel_log2 > 3) return bad("subpixel_log2 must lie in 0..3");
     if ((p->max_disparity << p->subpixel_log2) > kMaxDisparity)
@@ -186,6 +188,13 @@ int build_tables(stixels_handle* h) {
     h->prior.c_dive = (float)to_grid(m.diving_cost, g);
     h->prior.tau_ord = m.ordering_tol_px << k;     // in bins
     h->prior.mean_eps = (float)std::ldexp((double)D, -22);
+    h->prior.exact = g >= 0 ? 1 : 0;
+    if (g < 0) {
+        // costs off the grid: FP32 sums are not exact, so there is no range
+        // to keep; every pose is admitted
+        h->pose_in_range = true;
+        return STIXELS_OK;
+    }
     // exactness: every prefix, cost and intermediate of the recurrence is a
     // multiple of 2^-g bounded by 2 (h+1) cmax plus the priors
     const double bound = 2.0 * (Hmax + 1) * cmax + fmaxp + tmaxp + h->prior.c_ord +
@@ -336,6 +345,8 @@ int compute_frame(stixels_handle* h, const float* d_disparity, int32_t width, in
         return fail(h, STIXELS_E_INVALID_ARG, "handle created for the batch API only (no workspace)");
     const hipStream_t st = static_cast<hipStream_t>(stream);
     DeviceModel m = device_model(h);
+    // costs off the grid run the fused kernel with stored links
+    const int path = h->prior.exact ? frame_path_of(h) : 2;
     if (pose) {
         if (!h->pose_in_range)
             return fail(h, STIXELS_E_RANGE,
@@ -354,7 +365,7 @@ int compute_frame(stixels_handle* h, const float* d_disparity, int32_t width, in
         m.horizon_row = pose->horizon_row;
     }
     const int waves = frame_waves(h->waves, height, width / h->s, h->num_cu);
-    if (frame_path_of(h) == 2) {
+    if (path == 2) {
         int grid = 0;
         persist::JobDesc job = persist::make_job_desc(h, d_disparity, width, height, *out);
         job.ground = m.ground;
@@ -440,6 +451,8 @@ int stixels_debug_stage_times(stixels_handle* h, const float* d_disparity, int32
         !out->overflow || out->capacity < 1 || width < h->s || width > h->Wmax || height < 1 ||
         height > h->Hmax || !h->d_po)
         return fail(h, STIXELS_E_INVALID_ARG, "invalid frame, output or batch-only handle");
+    if (!h->prior.exact)
+        return fail(h, STIXELS_E_INVALID_ARG, "costs off the grid run the fused path only");
     const hipStream_t st = static_cast<hipStream_t>(stream);
     const int ncols = width / h->s;
     const int vtop = ground_top(h->p.camera.horizon_row, height);
@@ -480,7 +493,9 @@ int stixels_set_frame_path(stixels_handle* h, int32_t path) {
     return STIXELS_OK;
 }
 
-int stixels_get_frame_path(const stixels_handle* h) { return h ? frame_path_of(h) : 0; }
+int stixels_get_frame_path(const stixels_handle* h) {
+    return h ? (h->prior.exact ? frame_path_of(h) : 2) : 0;
+}
 
 int stixels_output_bytes(const stixels_handle* h, int32_t width, int32_t height, size_t* bytes) {
     int32_t ncols = 0, cap = 0;

@@ -30,10 +30,10 @@ hipError_t launch_pair_batch(int slots, int nch, int grid, hipStream_t st, const
     return hipLaunchKernel(f, dim3(grid), dim3(64), args, 0, st);
 }
 
-hipError_t launch_batch(int slots, int nch, int waves, int grid, hipStream_t st,
+hipError_t launch_batch(int slots, int nch, int waves, bool links, int grid, hipStream_t st,
                         const JobDesc* jobs, const int2* tasks, int ntasks, unsigned int* counter,
                         float* scratch, long long stride, int hmax) {
-    const void* f = batch_kernel_ptr(slots, nch, waves);
+    const void* f = links ? batch_links_kernel_ptr(slots, nch) : batch_kernel_ptr(slots, nch, waves);
     if (!f) return hipErrorInvalidValue;
     // stagger the XCDs' starts only where the tasks fill two rounds or more
     // of the resident workgroups (a shorter launch would only be delayed)
@@ -77,6 +77,7 @@ struct stixels_batch {
     int columns = 1;        // requested columns per wave (2: the pair kernel where it exists)
     int last_columns = 0;
     int last_grid = 0, last_tasks = 0, last_waves = 0;
+    bool links = false;     // the staged jobs need the recurrence with stored links
     std::string err;
 };
 
@@ -94,10 +95,11 @@ int batch_waves_for(const stixels_batch* b, int slots) {
     return std::min(std::max(b->waves, 1), cap);
 }
 
-int occupancy_grid(stixels_batch* b, int slots, int nch, int waves, int* grid) {
+int occupancy_grid(stixels_batch* b, int slots, int nch, int waves, int* grid,
+                   bool links = false) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_ptr(slots, nch, waves),
-                                                     64 * waves, 0) != hipSuccess ||
+    const void* f = links ? batch_links_kernel_ptr(slots, nch) : batch_kernel_ptr(slots, nch, waves);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * waves, 0) != hipSuccess ||
         per_cu < 1)
         return bfail(b, STIXELS_E_HIP, "occupancy query failed");
     *grid = per_cu * b->num_cu;
@@ -141,9 +143,11 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     int t = 0;
     b->npose = 0;
     b->pose_hmax = 0;
+    b->links = false;
     for (int i = 0; i < n; ++i) {
         const stixels_job& j = jobs[i];
         b->h_jobs[i] = make_job_desc(j.handle, j.d_disparity, j.width, j.height, j.out);
+        b->links = b->links || !j.handle->prior.exact;
         if (!j.use_pose) continue;
         if (!b->d_pose_area)
             return bfail(b, STIXELS_E_INVALID_ARG, "job " + std::to_string(i) +
@@ -169,7 +173,8 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     }
     // two columns per wave only where that kernel exists (h <= 512,
     // d_range <= 128); a task is then a (frame, even column) pair
-    const bool pairs = want_pairs && kernel_slots(hmax) <= 8 && kernel_chunks(dmax) == 2;
+    const bool pairs = want_pairs && !b->links && kernel_slots(hmax) <= 8 &&
+                       kernel_chunks(dmax) == 2;
     for (int oi = 0; oi < n; ++oi) {
         const int i = order[oi];
         const int nc = b->h_jobs[i].ncols;
@@ -197,7 +202,8 @@ int pair_occupancy_grid(stixels_batch* b, int slots, int nch, int* grid) {
 int choose_grid(stixels_batch* b, int slots, int nch, int waves, bool pairs, long long stride,
                 int ntasks, int* grid) {
     int g = 0;
-    int rc = pairs ? pair_occupancy_grid(b, slots, nch, &g) : occupancy_grid(b, slots, nch, waves, &g);
+    int rc = pairs ? pair_occupancy_grid(b, slots, nch, &g)
+                   : occupancy_grid(b, slots, nch, waves, &g, b->links);
     if (rc != STIXELS_OK) return rc;
     if (b->cfg.workgroups > 0) g = std::min(g, (int)b->cfg.workgroups);
     const long long by_scratch = (long long)(b->scratch_floats / (size_t)stride);
@@ -330,7 +336,7 @@ int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     long long stride = 0;
     bool pairs = false;
     int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax, b->columns == 2, &pairs);
-    const int waves = pairs ? 1 : batch_waves_for(b, slots);
+    const int waves = (pairs || b->links) ? 1 : batch_waves_for(b, slots);
     if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, pairs, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -340,7 +346,7 @@ int stixels_batch_compute(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (e == hipSuccess)
         e = pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs, b->d_tasks, ntasks,
                                   b->d_counter, b->d_scratch, stride, hmax)
-              : launch_batch(slots, nch, waves, grid, st, b->d_jobs, b->d_tasks, ntasks,
+              : launch_batch(slots, nch, waves, b->links, grid, st, b->d_jobs, b->d_tasks, ntasks,
                              b->d_counter, b->d_scratch, stride, hmax);
     if (e != hipSuccess)
         return bfail(b, STIXELS_E_HIP, std::string("batch launch failed: ") + hipGetErrorString(e));
@@ -359,7 +365,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     long long stride = 0;
     bool pairs = false;
     int rc = stage(b, jobs, n, &slots, &nch, &ntasks, &stride, &hmax, b->columns == 2, &pairs);
-    const int waves = pairs ? 1 : batch_waves_for(b, slots);
+    const int waves = (pairs || b->links) ? 1 : batch_waves_for(b, slots);
     if (rc == STIXELS_OK) rc = choose_grid(b, slots, nch, waves, pairs, stride, ntasks, &grid);
     if (rc != STIXELS_OK) return rc;
     const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -376,7 +382,7 @@ int stixels_batch_capture(stixels_batch* b, const stixels_job* jobs, int32_t n, 
     if (e == hipSuccess)
         e = pairs ? launch_pair_batch(slots, nch, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
                                   b->d_counter_g, b->d_scratch, stride, hmax)
-              : launch_batch(slots, nch, waves, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
+              : launch_batch(slots, nch, waves, b->links, grid, st, b->d_jobs_g, b->d_tasks_g, ntasks,
                              b->d_counter_g, b->d_scratch, stride, hmax);
     hipGraph_t g = nullptr;
     const hipError_t e2 = hipStreamEndCapture(st, &g);

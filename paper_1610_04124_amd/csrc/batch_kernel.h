@@ -75,14 +75,15 @@ constexpr int batch_waves(int slots_per_wave, int waves) {
     return slots_per_wave <= 7 ? (waves == 1 ? 5 : 4) : (slots_per_wave <= 14 ? 3 : 2);
 }
 
-// One workgroup of W waves per column task.
-template <int S, int NCH, int W>
+// One workgroup of W waves per column task.  LINKS: the recurrence keeps
+// its links and the backtracking follows them (costs off the grid).
+template <int S, int NCH, int W, bool LINKS = false>
 __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch_kernel(
     const JobDesc* __restrict__ jobs, const int2* __restrict__ tasks, int ntasks,
     unsigned int* counter, float* scratch, long long scratch_stride, int hmax,
     unsigned int stagger) {
-    __shared__ ColumnLds<S, W, 64 * NCH> lds;
+    __shared__ ColumnLds<S, W, 64 * NCH, LINKS> lds;
     // the column's reduced pixels live in the object row-cost array, which
     // solve_column writes only after its last read of them
     int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
@@ -280,13 +281,15 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         in.D = D;
         in.fg_hi = J.fg_hi;
         in.fg_lo = J.fg_lo;
+        in.S_tab = J.sky;
+        in.G_tab = J.ground;
         ColumnOut out;
         out.count = J.counts + col;
         out.rec = J.records + (size_t)col * J.cap * 3;
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
-        solve_column<S, NCH, W>(H, J.vtop, J.prior, in, out, lds);
+        solve_column<S, NCH, W, false, true, LINKS>(H, J.vtop, J.prior, in, out, lds);
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
 }

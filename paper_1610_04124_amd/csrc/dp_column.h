@@ -51,11 +51,24 @@ struct ColumnIn {
     const int32_t* fg_lo;   // gravity threshold per top-down image row
     float* rowc;            // [4][H+1] final object, ground, sky cost and best mean (bits) of
                             // every row, for the two-column recurrence only
+    const float* S_tab;     // [D] sky cost per pixel disparity (costs off the grid only)
+    const float* G_tab;     // [rows][D] ground cost by top-down row (costs off the grid only)
+};
+
+// Cut position b of the best stixel of each class ending at every row (the
+// index table of Sec. 3.3), kept by the recurrence variant for costs that
+// are not on a grid, whose backtracking cannot recover links by exact
+// recomputation.
+template <int S, bool LINKS>
+struct LinkRows {};
+template <int S>
+struct LinkRows<S, true> {
+    int16_t b[3][64 * S];
 };
 
 // Per-workgroup LDS of one column (S slots, W waves, QT prior-table entries
 // per wave: 64 per disparity chunk).
-template <int S, int W, int QT = 256>
+template <int S, int W, int QT = 256, bool LINKS = false>
 struct ColumnLds {
     float qtab[W][QT];      // per wave: prior minus PO[f][b] over the disparity rows
     float crow_g[64 * S];   // final GR^k of every row
@@ -63,6 +76,7 @@ struct ColumnLds {
     float crow_o[64 * S];   // final OB^k
     uint8_t crow_f[64 * S]; // mean - fbase of the best object stixel ending at k
     float bc[2][4];         // row j's values for the other waves (double-buffered)
+    LinkRows<S, LINKS> lk;  // object, ground, sky links (LINKS only)
 };
 
 struct ColumnOut {
@@ -278,6 +292,134 @@ __device__ void backtrack_column(const int H, const int vtop, const Prior P, con
     }
 }
 
+// Backtracking along stored links (Sec. 3.3, Sec. 4.4) by one wave64, for
+// the recurrence variant that keeps them (L.lk): the cut position of each
+// row's best stixel per class is read, and the predecessor class is the
+// first class (object, ground, sky) attaining the minimum the recurrence
+// took at that cut, recomputed from the same operands with the same
+// operations, hence bit for bit.  On the cost grid a stixel's cost is the
+// difference of two row costs (exact); off the grid (P.exact = 0) its data
+// term is summed directly over its pixels, recovered from the integer
+// prefixes (2q+1 and 2 per valid pixel), so that prefix cancellation does
+// not enter the reported cost, and its prior is added from the constants.
+template <int S, class Lds>
+__device__ void backtrack_links(const int H, const int vtop, const Prior P, const ColumnIn& in,
+                                const ColumnOut& out, const Lds& L) {
+    const int lane = threadIdx.x & 63;
+    const int fbase = in.fbase;
+    const float INF = inf_f();
+    const int ktop = H - 1;
+    float total = L.crow_o[ktop];
+    int ctop = 0;
+    {
+        const float g = L.crow_g[ktop], sk = L.crow_s[ktop];
+        if (g < total) { total = g; ctop = 1; }
+        if (sk < total) { total = sk; ctop = 2; }
+    }
+    // data term of stixel [b, k] of class cls (mean f) as a direct sum
+    auto direct = [&](int cls, int b, int k, int f) -> float {
+        float acc = 0.0f;
+        for (int v0 = b; v0 <= k; v0 += 64) {
+            const int v = v0 + lane;
+            if (v <= k && in.PN2[v + 1] != in.PN2[v]) {
+                const int q = (int)((in.PA[v + 1] - in.PA[v] - 1.0f) * 0.5f);
+                acc += (cls == 0) ? in.O_df[q * in.D + f]
+                                  : ((cls == 1) ? in.G_tab[(size_t)(H - 1 - v) * in.D + q]
+                                                : in.S_tab[q]);
+            }
+        }
+        return readlane_f(wave_inclusive_scan(acc), 63);
+    };
+    auto walk = [&](bool direct_write, int n_total, RecRegs& rr) -> int {
+        int k = ktop, cls = ctop, t = 0;
+        float target = total;
+        while (true) {
+            const int b = (int)L.lk.b[cls][k];
+            const int f = (cls == 0) ? (int)L.crow_f[k] + fbase : 0;
+            int cp = -1;
+            float prevC = 0.0f, prior = pick3(P.first[0], P.first[1], P.first[2], cls);
+            if (b > 0) {
+                const int p = b - 1;
+                const float Co = L.crow_o[p], Cg = L.crow_g[p], Cs = L.crow_s[p];
+                float x0, x1, x2, pen0 = 0.0f, pen1 = 0.0f;
+                if (cls == 0) {
+                    const float Xoo = Co + P.trans[0][0];
+                    const bool ord = f > (int)L.crow_f[p] + fbase + P.tau_ord;
+                    x0 = ord ? Xoo + P.c_ord : Xoo;
+                    pen0 = ord ? P.c_ord : 0.0f;
+                    x1 = INF;
+                    if (b <= vtop + 1) {          // steps with the ground terms
+                        const int r = H - 1 - b;
+                        const int thi = in.fg_hi[r], tlo = in.fg_lo[r];
+                        const float Xgo = Cg + P.trans[1][0];
+                        x1 = (f < tlo) ? Xgo + P.c_grav : Xgo;
+                        pen1 = (f < tlo) ? P.c_grav : 0.0f;
+                        if (f > thi) {
+                            x1 = Xgo + P.c_dive;
+                            pen1 = P.c_dive;
+                        }
+                    }
+                    x2 = Cs + P.trans[2][0];
+                } else {
+                    x0 = Co + pick3(P.trans[0][0], P.trans[0][1], P.trans[0][2], cls);
+                    x1 = Cg + pick3(P.trans[1][0], P.trans[1][1], P.trans[1][2], cls);
+                    x2 = Cs + pick3(P.trans[2][0], P.trans[2][1], P.trans[2][2], cls);
+                }
+                const float m = vmin(vmin(x0, x1), x2);
+                cp = (x0 == m) ? 0 : ((x1 == m) ? 1 : 2);
+                prevC = pick3(Co, Cg, Cs, cp);
+                prior = pick3(P.trans[0][cls], P.trans[1][cls], P.trans[2][cls], cp) +
+                        ((cp == 0) ? pen0 : ((cp == 1) ? pen1 : 0.0f));
+            }
+            float cost;
+            if (P.exact) {
+                cost = (b > 0) ? target - prevC : target;
+            } else {
+                cost = direct(cls, b, k, f) + prior;
+            }
+            const int fout = (cls == 0) ? f : 0;
+            if (!direct_write) {
+                if (lane == t) pack_record(b, k, cls, fout, cost, rr.w0, rr.w1, rr.w2);
+            } else {
+                const int pos = n_total - 1 - t;
+                if (pos < out.cap && lane == 0) {
+                    uint32_t w0, w1;
+                    float w2;
+                    pack_record(b, k, cls, fout, cost, w0, w1, w2);
+                    out.rec[pos * 3 + 0] = w0;
+                    out.rec[pos * 3 + 1] = w1;
+                    out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, w2);
+                }
+            }
+            ++t;
+            if (b == 0 || t > H) break;
+            k = b - 1;
+            cls = cp;
+            target = prevC;
+        }
+        return t;
+    };
+
+    RecRegs rr{0u, 0u, 0.0f};
+    const int n = walk(false, 0, rr);
+    if (n <= 64) {
+        const int pos = n - 1 - lane;
+        if (lane < n && pos < out.cap) {
+            out.rec[pos * 3 + 0] = rr.w0;
+            out.rec[pos * 3 + 1] = rr.w1;
+            out.rec[pos * 3 + 2] = __builtin_bit_cast(uint32_t, rr.w2);
+        }
+    } else {
+        RecRegs dummy{0u, 0u, 0.0f};
+        walk(true, n, dummy);
+    }
+    if (lane == 0) {
+        *out.count = n < out.cap ? n : out.cap;
+        *out.total = total;
+        *out.overflow = (uint8_t)(n > out.cap ? 1 : 0);
+    }
+}
+
 // S: 64-row slots (h <= 64 S); NCH: 64-entry chunks of disparity rows
 // (d_range <= 64 NCH); W: waves per column (the workgroup is 64 W lanes, all
 // of which call this function).  POL: the recurrence gathers the object
@@ -285,10 +427,12 @@ __device__ void backtrack_column(const int H, const int vtop, const Prior P, con
 // reads in.PO).  BLOCKS: short columns read their steps' wave-uniform
 // values a slot at a time (right for many waves per SIMD, which hide the
 // load at each slot boundary; a column alone on its SIMD keeps the per-step
-// prefetch).  On return the results are written.
-template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true>
+// prefetch).  LINKS: also keep the cut position of every row's best stixel
+// per class (one select per candidate) and backtrack along those links, for
+// costs off the grid.  On return the results are written.
+template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false>
 __device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
-                             const ColumnOut& out, ColumnLds<S, W, 64 * NCH>& L,
+                             const ColumnOut& out, ColumnLds<S, W, 64 * NCH, LINKS>& L,
                              const float* po_lds = nullptr) {
     static_assert(W == 1 || W == 2 || W == 4, "waves per column");
     constexpr int SW = (S + W - 1) / W;              // slots per wave
@@ -322,6 +466,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     float eA[SW], eN[SW];               // prefix values at k+1 (mean numerator, 2 n)
     float mO[SW];                       // OB^k so far
     int fO[SW];                         // mean (- fbase) of the best object stixel ending at k
+    int bO[LINKS ? SW : 1];             // its cut position (LINKS)
 
     // Slots past the column's height (a shorter frame in a batch sized for
     // taller ones, or the last slot of a wave when W does not divide S) are
@@ -332,6 +477,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
     for (int t = 0; t < SW; ++t) {
         const int s = t * W + wave;
+        if constexpr (LINKS) bO[t] = 0;
         if (s >= nslots) {
             mO[t] = INF;
             eA[t] = eN[t] = 0.0f;
@@ -431,6 +577,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // and a row's ground and sky costs are written once, when the row is
     // reached, instead of being folded per row and per step.
     float RG = P.first[1], RS = P.first[2];
+    int bRG = 0, bRS = 0;               // cut positions of the minima (LINKS)
 
     // Push-form recurrence: step j finalises row j and folds the stixels
     // that start at b = j+1 into every row k > j.  Per step, the prior of an
@@ -528,6 +675,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 const bool better = cO < mO[t];
                 mO[t] = better ? cO : mO[t];
                 fO[t] = better ? fS[t] : fO[t];
+                if constexpr (LINKS) bO[t] = better ? b : bO[t];
             }
         };
         auto group_open = [&](int g0) {
@@ -551,6 +699,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         if (wave == 0 && lane == 0) {
             L.crow_g[j] = Cg;
             L.crow_s[j] = Cs;
+            if constexpr (LINKS) {
+                L.lk.b[1][j] = (int16_t)bRG;
+                L.lk.b[2][j] = (int16_t)bRS;
+            }
         }
         // bounds at base row b
         const int thi = BLK ? readlane_i(blk.thi, jl) : thi_n;
@@ -561,6 +713,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
+        if constexpr (LINKS) bRS = (XS < RS) ? b : bRS;
         RS = vmin(RS, XS);
         const float Xoo = Co + P.trans[0][0];
         const float Xoo_p = Xoo + P.c_ord;
@@ -571,6 +724,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             XG = (b <= vtop)
                 ? vmin(vmin(Co + P.trans[0][1], Cg + P.trans[1][1]), Cs + P.trans[2][1]) - bG
                 : INF;
+            if constexpr (LINKS) bRG = (XG < RG) ? b : bRG;
             RG = vmin(RG, XG);
             Xgo = Cg + P.trans[1][0];
             Xgo_d = Xgo + P.c_dive;
@@ -660,6 +814,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     if (wave == 0 && lane == 0) {
         L.crow_g[H - 1] = ((H - 1 <= vtop) ? buf_load(pgr, H) : INF) + RG;
         L.crow_s[H - 1] = buf_load(psr, H) + RS;
+        if constexpr (LINKS) {
+            L.lk.b[1][H - 1] = (int16_t)bRG;
+            L.lk.b[2][H - 1] = (int16_t)bRS;
+        }
     }
 #pragma unroll
     for (int t = 0; t < SW; ++t) {
@@ -667,12 +825,17 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         if (s < S) {
             L.crow_o[s * 64 + lane] = mO[t];
             L.crow_f[s * 64 + lane] = (uint8_t)fO[t];
+            if constexpr (LINKS) L.lk.b[0][s * 64 + lane] = (int16_t)bO[t];
         }
     }
     __syncthreads();
     if (wave != 0) return;
 
-    backtrack_column<S>(H, vtop, P, in, out, L);
+    if constexpr (LINKS) {
+        backtrack_links<S>(H, vtop, P, in, out, L);
+    } else {
+        backtrack_column<S>(H, vtop, P, in, out, L);
+    }
 }
 
 

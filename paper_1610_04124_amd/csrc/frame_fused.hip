@@ -35,8 +35,10 @@ hipError_t launch_frame_fused(const JobDesc& job, void* ws, size_t ws_bytes, int
     *grid_out = 0;
     const int slots = kernel_slots(job.H), nch = kernel_chunks(job.D);
     const int cap = slots >= 4 ? 4 : (slots >= 2 ? 2 : 1);
-    waves = std::min(std::max(waves, 1), cap);
-    const void* f = batch_kernel_ptr(slots, nch, waves);
+    // costs off the grid: the recurrence with stored links, one wave
+    const bool links = !job.prior.exact;
+    waves = links ? 1 : std::min(std::max(waves, 1), cap);
+    const void* f = links ? batch_links_kernel_ptr(slots, nch) : batch_kernel_ptr(slots, nch, waves);
     if (!f || job.ncols < 1) return hipErrorInvalidValue;
     const size_t base = frame_fused_bytes(job.ncols, job.H, job.D, 0);
     if (ws_bytes < base) return hipErrorInvalidValue;

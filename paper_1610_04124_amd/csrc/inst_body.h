@@ -28,6 +28,14 @@ const void* pick_batch(int nch, int waves) {
 }
 
 template <int N, int C>
+const void* pick_links(int nch) {
+    if constexpr (N == STX_SLOTS) {
+        if (nch == C) return reinterpret_cast<const void*>(&persist::batch_kernel<N, C, 1, true>);
+    }
+    return nullptr;
+}
+
+template <int N, int C>
 const void* pick_pair(int nch) {
     if constexpr (N == STX_SLOTS) {
         if (nch == C) return reinterpret_cast<const void*>(&persist::batch_pair_kernel<N, C>);
@@ -56,6 +64,14 @@ const void* STX_CAT(batch_kernel_ptr_s, STX_SLOTS)(int nch, int waves) {
 #define STX_CASE(n, c, w) \
     if (const void* p = pick_batch<n, c, w>(nch, waves)) return p;
     STX_FOR_EACH_VARIANT(STX_CASE)
+#undef STX_CASE
+    return nullptr;
+}
+
+const void* STX_CAT(batch_links_kernel_ptr_s, STX_SLOTS)(int nch) {
+#define STX_CASE(n, c) \
+    if (const void* p = pick_links<n, c>(nch)) return p;
+    STX_FOR_EACH_LINKS_VARIANT(STX_CASE)
 #undef STX_CASE
     return nullptr;
 }

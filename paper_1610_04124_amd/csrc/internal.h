@@ -52,6 +52,15 @@ __host__ __device__ constexpr int kernel_chunks(int d_range) { return d_range <=
     X(10, 4, 2) X(10, 4, 4) X(12, 4, 1) X(12, 4, 2) X(12, 4, 4) X(14, 4, 1) X(14, 4, 2) \
     X(14, 4, 4) X(16, 4, 1) X(16, 4, 2) X(16, 4, 4)
 
+// Variants of the recurrence that keep an index table of cut positions
+// (Sec. 3.3) for the backtracking, used by handles whose costs are not on a
+// grid (cost_grid_log2 = -1): one wave per column, every slot count and
+// disparity chunk count.
+#define STX_FOR_EACH_LINKS_VARIANT(X) \
+    X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2) X(10, 2) X(12, 2) \
+    X(14, 2) X(16, 2) X(1, 4) X(2, 4) X(3, 4) X(4, 4) X(5, 4) X(6, 4) X(7, 4) X(8, 4) \
+    X(10, 4) X(12, 4) X(14, 4) X(16, 4)
+
 // Slot counts of the two-columns-per-wave recurrence (d_range <= 128, h <= 512).
 #define STX_FOR_EACH_PAIR_VARIANT(X) \
     X(1, 2) X(2, 2) X(3, 2) X(4, 2) X(5, 2) X(6, 2) X(7, 2) X(8, 2)
@@ -63,6 +72,7 @@ struct Prior {
     float c_ord, c_grav, c_dive;
     int tau_ord;
     float mean_eps;       // bias of the rounded-mean division, d_range * 2^-22
+    int exact;            // 1: every cost is on the 2^-g grid (FP32 sums are exact)
 };
 
 // Per-frame geometry shared by the kernels.

@@ -14,6 +14,7 @@ namespace stx {
 
 #define STX_DECLARE_SLOTS(n)                                                   \
     const void* batch_kernel_ptr_s##n(int nch, int waves);                     \
+    const void* batch_links_kernel_ptr_s##n(int nch);                          \
     const void* batch_pair_kernel_ptr_s##n(int nch);                           \
     const void* dp_kernel_ptr_s##n(int nch, int waves, bool pol);
 STX_FOR_EACH_SLOTS(STX_DECLARE_SLOTS)
@@ -21,6 +22,9 @@ STX_FOR_EACH_SLOTS(STX_DECLARE_SLOTS)
 
 // persistent batched kernel <slots, disparity chunks, waves per column>
 const void* batch_kernel_ptr(int slots, int nch, int waves);
+// persistent batched kernel with stored links, one wave per column
+// <slots, disparity chunks> (costs off the grid)
+const void* batch_links_kernel_ptr(int slots, int nch);
 // two columns per wave <slots, disparity chunks>
 const void* batch_pair_kernel_ptr(int slots, int nch);
 // staged per-frame recurrence <slots, disparity chunks, waves, LDS table copy>

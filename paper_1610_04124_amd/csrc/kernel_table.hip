@@ -12,6 +12,15 @@ const void* batch_kernel_ptr(int slots, int nch, int waves) {
     }
 }
 
+const void* batch_links_kernel_ptr(int slots, int nch) {
+    switch (slots) {
+#define STX_CASE(n) case n: return batch_links_kernel_ptr_s##n(nch);
+        STX_FOR_EACH_SLOTS(STX_CASE)
+#undef STX_CASE
+        default: return nullptr;
+    }
+}
+
 const void* batch_pair_kernel_ptr(int slots, int nch) {
     switch (slots) {
 #define STX_CASE(n) case n: return batch_pair_kernel_ptr_s##n(nch);

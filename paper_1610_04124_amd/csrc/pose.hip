@@ -47,7 +47,7 @@ __device__ void pose_row(const PoseItem& it, int r) {
             const double gs = k_c + (x - mu) * (x - mu) / k_2s2;
             double c = it.c_out;
             if (isfinite(gs) && gs < c) c = gs;
-            v = (float)ldexp(rint(ldexp(c, it.g)), -it.g);
+            v = (it.g >= 0) ? (float)ldexp(rint(ldexp(c, it.g)), -it.g) : (float)c;
         }
         it.G[(size_t)r * it.D + d] = v;
     }

@@ -188,3 +188,17 @@ def test_subpixel_limits(kw, code):
     with pytest.raises(B.StixelsError) as e:
         P.host_table(p, B.TABLE_SKY)
     assert e.value.code == code
+
+
+def test_host_tables_off_the_grid_equal_oracle_in_fp32():
+    """cost_grid_log2 = -1: no rounding onto a grid; the library's FP32
+    tables are the oracle's FP64 values rounded once to FP32."""
+    p = synth.make_params(camera=synth.CAMERA_1024x440, cost_grid_log2=-1)
+    H = p["max_height"]
+    t = oracle.tables(p, H)
+    assert np.array_equal(P.host_table(p, B.TABLE_SKY), t["S"].astype(np.float32))
+    assert np.array_equal(P.host_table(p, B.TABLE_GROUND)[::-1], t["G"].astype(np.float32))
+    assert np.array_equal(P.host_table(p, B.TABLE_OBJECT).T, t["O"].astype(np.float32))
+    assert np.array_equal(P.host_table(p, B.TABLE_FG_HI)[::-1], t["fg_hi"][:H])
+    # some table value really is off the 2^-10 grid
+    assert np.any(np.ldexp(t["S"], 10) != np.rint(np.ldexp(t["S"], 10)))
