@@ -210,6 +210,15 @@ int stixels_compute_pose(stixels_handle *h, const float *d_disparity, int32_t wi
  * staged call.  STIXELS_E_INVALID_ARG for other values. */
 int stixels_set_frame_path(stixels_handle *h, int32_t path);
 
+/* Object costs of the staged path's prefix-table kernel (Sec. 4.2): 0 (the
+ * default) = the offline LUT of Sec. 3.4, one table lookup per (pixel,
+ * mean); 1 = Eq. 4 evaluated online per (pixel, mean) in FP64 from a per-mean
+ * constant (its normalisation) and rounded to the grid, as the paper's
+ * online alternative that its offline LUT replaced.  Results do not depend
+ * on it (the online values equal the LUT's bit for bit); the fused and batch
+ * paths always use the LUT.  STIXELS_E_INVALID_ARG for other values. */
+int stixels_set_object_lut(stixels_handle *h, int32_t mode);
+
 /* The path (1 or 2) stixels_compute takes under the current setting (0 for a
  * null handle). */
 int stixels_get_frame_path(const stixels_handle *h);

@@ -36,6 +36,7 @@ EXPORTS = (
     "stixels_compute_batch", "stixels_debug_tables", "stixels_set_frame_path",
     "stixels_get_frame_path", "stixels_device_bytes", "stixels_batch_device_bytes",
     "stixels_debug_stage_times", "stixels_compute_pose", "stixels_debug_pose_tables",
+    "stixels_set_object_lut",
 )
 
 
@@ -150,6 +151,7 @@ def lib():
         L.stixels_compute_batch.argtypes = [P(Job), i32, vp]
         L.stixels_debug_tables.argtypes = [vp, vp, C.c_size_t]
         L.stixels_set_frame_path.argtypes = [vp, i32]
+        L.stixels_set_object_lut.argtypes = [vp, i32]
         L.stixels_get_frame_path.argtypes = [vp]
         L.stixels_device_bytes.argtypes = [vp, P(C.c_size_t)]
         L.stixels_batch_device_bytes.argtypes = [vp, P(C.c_size_t)]
@@ -315,6 +317,12 @@ class Stixels:
         rc = lib().stixels_set_frame_path(self.h, int(path))
         if rc != OK:
             self._err(rc, "stixels_set_frame_path")
+
+    def set_object_lut(self, mode: int) -> None:
+        """Object costs of the staged table build: 0 offline LUT, 1 online Eq. 4."""
+        rc = lib().stixels_set_object_lut(self.h, int(mode))
+        if rc != OK:
+            self._err(rc, "stixels_set_object_lut")
 
     def frame_path(self) -> int:
         """The path (1 staged, 2 fused) compute takes under the current setting."""

@@ -119,6 +119,7 @@ void release(stixels_handle* h) {
     (void)hipFree(h->d_pose_ground);
     (void)hipFree(h->d_pose_hi);
     (void)hipFree(h->d_pose_lo);
+    (void)hipFree(h->d_obj_k);
 }
 
 // Offline tables (Sec. 3.4) in FP64, rounded to the grid and stored as FP32.
@@ -158,12 +159,19 @@ int build_tables(stixels_handle* h) {
         h->fg_hi[r] = (int32_t)std::floor(std::ldexp(mu + m.diving_tol_px, k));
         h->fg_lo[r] = (int32_t)std::ceil(std::ldexp(mu - m.gravity_tol_px, k));
     }
-    // object table stored as [f][d]: one row per model mean f
+    // object table stored as [f][d]: one row per model mean f; beside it the
+    // part of Eq. 4 that depends on the mean only (for online evaluation)
     h->object_t.resize((size_t)D * D);
+    h->obj_k.resize((size_t)2 * D);
+    h->c_out = std::log(dr) - std::log(m.p_out);
     for (int f = 0; f < D; ++f) {
         const double e = px(f) * px(f) * m.object_depth_extent_m /
                          (p.camera.focal_px * p.camera.baseline_m);
         const double so = std::sqrt(m.sigma_disp * m.sigma_disp + e * e);
+        const double mass = gauss_cdf((dr - px(f)) / so) - gauss_cdf(-px(f) / so);
+        h->obj_k[2 * f] = std::log(mass) + std::log(so * std::sqrt(2.0 * M_PI)) -
+                          std::log(1.0 - m.p_out);
+        h->obj_k[2 * f + 1] = 2.0 * so * so;
         for (int d = 0; d < D; ++d)
             h->object_t[(size_t)f * D + d] = keep(to_grid(pixel_cost(px(d), px(f), so, m.p_out, dr), g));
     }
@@ -260,6 +268,7 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     if (rc == STIXELS_OK) rc = upload(h, &h->d_object_df, h->object_df);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_hi, h->fg_hi);
     if (rc == STIXELS_OK) rc = upload(h, &h->d_fg_lo, h->fg_lo);
+    if (rc == STIXELS_OK) rc = upload(h, &h->d_obj_k, h->obj_k);
     if (rc == STIXELS_OK && !(params->flags & STIXELS_FLAG_BATCH_ONLY)) {
         const size_t nc = (size_t)h->ncols_max, H1 = (size_t)h->Hmax + 1;
         // d_po holds the staged path's object prefix tables or, for the
@@ -490,6 +499,14 @@ int stixels_set_frame_path(stixels_handle* h, int32_t path) {
     if (path < 0 || path > 2)
         return fail(h, STIXELS_E_INVALID_ARG, "frame path must be 0 (auto), 1 (staged) or 2 (fused)");
     h->frame_path = path;
+    return STIXELS_OK;
+}
+
+int stixels_set_object_lut(stixels_handle* h, int32_t mode) {
+    if (!h) return STIXELS_E_INVALID_ARG;
+    if (mode != 0 && mode != 1)
+        return fail(h, STIXELS_E_INVALID_ARG, "object LUT mode must be 0 (offline) or 1 (online)");
+    h->object_lut = mode;
     return STIXELS_OK;
 }
 

@@ -61,8 +61,25 @@ struct TablesArgs {
     const float* sky;
     const float* ground;
     const float* object_t;
+    // online object costs (instead of the offline LUT of Sec. 3.4): per mean
+    // f, the Gaussian's constant part and 2 sigma^2 (FP64), the outlier cost
+    const double* obj_k;
+    double c_out;
+    int online, g, sub;
     int H, ncols, D;
 };
+
+// Eq. 4 for pixel bin q against mean bin f, evaluated in FP64 from the
+// mean's constant part k[2f] and its 2 sigma^2 k[2f+1] with the operations
+// and order of the offline table build, then rounded to the grid: equal to
+// the offline LUT entry bit for bit.
+__device__ __forceinline__ float object_cost_online(const TablesArgs& a, int q, int f) {
+    const double x = ldexp((double)q, -a.sub), mu = ldexp((double)f, -a.sub);
+    const double gs = a.obj_k[2 * f] + (x - mu) * (x - mu) / a.obj_k[2 * f + 1];
+    double c = a.c_out;
+    if (isfinite(gs) && gs < c) c = gs;
+    return (a.g >= 0) ? (float)ldexp(rint(ldexp(c, a.g)), -a.g) : (float)c;
+}
 
 __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
     __shared__ int16_t qs[kMaxHeight];
@@ -166,10 +183,20 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
     for (int f = f0 + wave; f <= f1; f += 8) {
         const uint32_t rowb = (uint32_t)(f * D) * 4u;
         float oc[kSlots];
+        if (a.online) {
 #pragma unroll
-        for (int c = 0; c < kSlots; ++c) {
-            if (c >= nsl) break;
-            oc[c] = buf_load_b(otr, qoff[c], rowb);
+            for (int c = 0; c < kSlots; ++c) {
+                if (c >= nsl) break;
+                const int v = 64 * c + lane;
+                const int x = (v < H) ? (int)qs[v] : -1;
+                oc[c] = (x >= 0) ? object_cost_online(a, x, f) : 0.0f;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < kSlots; ++c) {
+                if (c >= nsl) break;
+                oc[c] = buf_load_b(otr, qoff[c], rowb);
+            }
         }
         const uint32_t rowoff = (uint32_t)(f - f0) * (uint32_t)stride * 4u;
         if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
@@ -246,6 +273,11 @@ hipError_t launch_tables(const DeviceModel& m, const FrameWorkspace& ws, int H, 
     a.sky = m.sky;
     a.ground = m.ground;
     a.object_t = m.object_t;
+    a.obj_k = m.obj_k;
+    a.c_out = m.c_out;
+    a.online = m.object_online;
+    a.g = m.g;
+    a.sub = m.sub;
     a.H = H;
     a.ncols = ncols;
     a.D = m.D;

@@ -23,6 +23,12 @@ struct DeviceModel {
     int s;
     double horizon_row;
     Prior prior;
+    // online object costs in the staged table build (Sec. 3.4 compares
+    // them with the offline LUT): per mean the constant part and 2 sigma^2
+    const double* obj_k = nullptr;
+    double c_out = 0.0;
+    int object_online = 0;
+    int g = 0;
 };
 
 // Per-frame workspace views.

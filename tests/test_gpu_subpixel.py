@@ -52,3 +52,29 @@ def test_subpixel_batch_with_whole_px_frames():
     torch.cuda.synchronize()
     for i, ((_, _, out), (p, disp)) in enumerate(zip(items, refs)):
         assert_frames_equal(out.to_host(), oracle.frame(p, disp), f"subpixel batch job {i}")
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(subpixel_log2=1), dict(cost_grid_log2=6),
+                                dict(max_disparity=256, max_width=2048, max_height=880)])
+def test_online_object_costs_equal_offline_lut(kw):
+    """Sec. 3.4: the staged table build with Eq. 4 evaluated online per
+    (pixel, mean) gives the offline LUT's prefix tables and stixels bit for
+    bit."""
+    announce(f"online object LUT {kw}")
+    W, H = kw.get("max_width", 1024), kw.get("max_height", 440)
+    cam = synth.camera_for_size(W, H)
+    p = synth.make_params(camera=cam, **{"max_width": W, "max_height": H, **kw})
+    h = P.Stixels(p)
+    h.set_frame_path(1)
+    disp = synth.generate_frame(synth.SceneSpec(W, H, p["max_disparity"], cam, seed=70))
+    off = gpu_frame(h, disp)
+    po_off = h.debug_stage(3, W, H)
+    h.set_object_lut(1)
+    on = gpu_frame(h, disp)
+    po_on = h.debug_stage(3, W, H)
+    rng = h.debug_stage(2, W, H)
+    for i in range(len(rng)):
+        n = rng[i, 1] - rng[i, 0] + 1
+        assert np.array_equal(po_on[i, :n], po_off[i, :n]), i
+    assert_frames_equal(on, oracle.frame(p, disp), "online LUT")
+    assert_frames_equal(off, oracle.frame(p, disp), "offline LUT")
