@@ -48,7 +48,7 @@ enum { STIXELS_OBJECT = 0, STIXELS_GROUND = 1, STIXELS_SKY = 2 };
 /* Stereo camera.  The ground slope in disparity per row is
  * baseline * cos(pitch) / height and the ground disparity of top-down image
  * row r is slope * (r - horizon_row) (Sec. 3.1, ground model).  horizon_row
- * must be a multiple of 1/256 with |horizon_row| <= 2^20. */
+ * must be a multiple of 1/256 with |horizon_row| <= 2^20; |pitch| < pi/2. */
 typedef struct {
     double focal_px, baseline_m, cam_height_m, horizon_row, pitch_rad;
 } stixels_camera;
@@ -140,8 +140,8 @@ typedef struct stixels_handle stixels_handle;
  * handle's ground table (Eq. 4 per row and pixel disparity) and the diving /
  * gravity thresholds are rebuilt on the device for the frame; the sky and
  * object tables do not depend on the pose.  Valid poses: horizon_row a
- * multiple of 1/256 with |horizon_row| <= 2^20, pitch finite with
- * cos(pitch) > 0, and a ground disparity at the frame's bottom row of at
+ * multiple of 1/256 with |horizon_row| <= 2^20, |pitch_rad| < pi/2
+ * (finite), and a ground disparity at the frame's bottom row of at
  * most max_disparity. */
 typedef struct {
     double horizon_row, pitch_rad;

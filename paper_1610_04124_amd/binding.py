@@ -391,13 +391,14 @@ class Stixels:
         """The kernels write ncols columns of `capacity` records into the
         output's tensors; a mismatched output would be overrun on the device."""
         if out.ncols != self.num_columns(width):
-            raise ValueError(f"output holds {out.ncols} columns, the frame has "
-                             f"{self.num_columns(width)}")
+            raise StixelsError(E_INVALID_ARG, f"output holds {out.ncols} columns, the frame "
+                               f"has {self.num_columns(width)}")
         if out.counts.device != device:
-            raise ValueError("output and input are on different devices")
+            raise StixelsError(E_INVALID_ARG, "output and input are on different devices")
         if (out.records.shape != (out.ncols, out.capacity, 3) or out.counts.numel() != out.ncols
                 or out.total.numel() != out.ncols or out.overflow.numel() != out.ncols):
-            raise ValueError("output tensors do not match its column count and capacity")
+            raise StixelsError(E_INVALID_ARG,
+                               "output tensors do not match its column count and capacity")
 
     def compute_raw(self, disp_ptr: int, W: int, H: int, out: Output, stream_ptr) -> None:
         rc = lib().stixels_compute(self.h, C.c_void_p(disp_ptr), int(W), int(H), stream_ptr,

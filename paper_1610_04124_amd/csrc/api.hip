@@ -50,8 +50,9 @@ int validate(const stixels_params* p, std::string& why) {
     const stixels_camera& c = p->camera;
     const stixels_model& m = p->model;
     auto bad = [&](const char* w) { why = w; return STIXELS_E_INVALID_ARG; };
-    if (!(c.focal_px > 0 && c.baseline_m > 0 && c.cam_height_m > 0 && std::isfinite(c.pitch_rad)))
-        return bad("camera focal, baseline and height must be > 0, pitch finite");
+    if (!(c.focal_px > 0 && c.baseline_m > 0 && c.cam_height_m > 0 &&
+          std::fabs(c.pitch_rad) < M_PI_2))
+        return bad("camera focal, baseline and height must be > 0, |pitch| < pi/2");
     if (!std::isfinite(c.horizon_row) || std::fabs(c.horizon_row) > 1048576.0 ||
         std::ldexp(c.horizon_row, 8) != std::rint(std::ldexp(c.horizon_row, 8)))
         return bad("horizon_row must be a multiple of 1/256 with |horizon_row| <= 2^20");

@@ -38,7 +38,7 @@ struct PoseItem {
 };
 
 // Checks a frame pose against a handle (horizon on the 1/256 grid, finite
-// pitch with cos > 0, the bottom row's ground disparity within [0, d_range]:
+// pitch with |pitch| < pi/2, the bottom row's ground disparity within [0, d_range]:
 // then every ground cost is bounded by the handle's exactness check) and
 // fills `it` for a frame of height H.  Returns STIXELS_OK or
 // STIXELS_E_INVALID_ARG with the reason in *why.

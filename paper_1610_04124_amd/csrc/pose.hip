@@ -73,9 +73,11 @@ int make_pose_item(const stixels_params& p, int D, const stixels_pose& pose, int
         *why = "pose horizon_row must be a multiple of 1/256 with |horizon_row| <= 2^20";
         return STIXELS_E_INVALID_ARG;
     }
+    // |pitch| < pi/2: the camera sees the ground plane from above (at pi/2
+    // the double nearest pi/2 still has cos > 0, a slope of ~1e-17 px/row)
     const double cp = std::cos(pose.pitch_rad);
-    if (!std::isfinite(pose.pitch_rad) || !(cp > 0.0)) {
-        *why = "pose pitch must be finite with cos(pitch) > 0";
+    if (!(std::fabs(pose.pitch_rad) < M_PI_2) || !(cp > 0.0)) {
+        *why = "pose pitch must be finite with |pitch| < pi/2";
         return STIXELS_E_INVALID_ARG;
     }
     const double alpha = c.baseline_m * cp / c.cam_height_m;

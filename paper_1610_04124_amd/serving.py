@@ -334,18 +334,27 @@ def poisson_arrivals(rates, seconds: float, seeds, frames_per_camera: int):
 SERVING_SIZES = [(1024, 440), (1280, 720), (2048, 880)]
 
 
-def serving_cameras(n_cameras: int = 8, stixel_width: int = 5):
-    """Handles and frame sizes of the serving workload (one handle per camera,
-    used through the batch API only, so without a per-frame workspace)."""
+def serving_params(camera: int, stixel_width: int = 5, batch_only: bool = True):
+    """Parameters of serving camera `camera` (frame size by camera index).
+    batch_only: a handle used through the batch API only, without a per-frame
+    workspace."""
     import synth
+    import paper_1610_04124_amd as P
+
+    W, H = SERVING_SIZES[camera % len(SERVING_SIZES)]
+    D = 256 if W == 2048 else 128
+    return synth.make_params(camera=synth.camera_for_size(W, H), stixel_width=stixel_width,
+                             max_disparity=D, max_width=W, max_height=H,
+                             flags=P.binding.FLAG_BATCH_ONLY if batch_only else 0)
+
+
+def serving_cameras(n_cameras: int = 8, stixel_width: int = 5):
+    """Handles and frame sizes of the serving workload (one batch-only handle
+    per camera)."""
     import paper_1610_04124_amd as P
 
     cams = []
     for i in range(n_cameras):
         W, H = SERVING_SIZES[i % len(SERVING_SIZES)]
-        D = 256 if W == 2048 else 128
-        p = synth.make_params(camera=synth.camera_for_size(W, H), stixel_width=stixel_width,
-                              max_disparity=D, max_width=W, max_height=H,
-                              flags=P.binding.FLAG_BATCH_ONLY)
-        cams.append(CameraSpec(P.Stixels(p), W, H))
+        cams.append(CameraSpec(P.Stixels(serving_params(i, stixel_width)), W, H))
     return cams

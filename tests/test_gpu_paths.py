@@ -129,7 +129,7 @@ def test_binding_rejects_mismatched_outputs():
     p, h = handle_for(1024, 440)
     disp = to_device(synth.generate_frame(synth.SceneSpec(seed=1)))
     wrong = h.new_output(1000, 440)            # 200 columns, the frame has 204
-    with pytest.raises(ValueError):
+    with pytest.raises(B.StixelsError):
         h.compute(disp, wrong)
-    with pytest.raises(ValueError):
+    with pytest.raises(B.StixelsError):
         P.Batch(1, 204, 440, 128).compute([(h, disp, wrong)])

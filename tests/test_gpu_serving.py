@@ -7,7 +7,9 @@ import pytest
 
 import synth
 from gpu_helpers import announce, to_device
-from paper_1610_04124_amd.serving import GpuExecutor, Server, poisson_arrivals, serving_cameras
+import paper_1610_04124_amd as P
+from paper_1610_04124_amd.serving import (GpuExecutor, Server, poisson_arrivals, serving_cameras,
+                                          serving_params)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,9 +26,12 @@ def test_served_frames_equal_alone():
             disp = synth.generate_frame(synth.SceneSpec(W, H, D, synth.camera_for_size(W, H),
                                                         seed=1000 * c + i))
             frames[(c, i)] = to_device(disp)
+    # alone: the per-frame path of a handle with the camera's parameters (the
+    # serving handles are batch-only)
+    solo = [P.Stixels(serving_params(c, batch_only=False)) for c in range(len(cams))]
     alone = {}
     for (c, i), f in frames.items():
-        alone[(c, i)] = cams[c].handle.compute(f)
+        alone[(c, i)] = solo[c].compute(f)
     torch.cuda.synchronize()
     key_of = {f.data_ptr(): k for k, f in frames.items()}
 
