@@ -188,6 +188,23 @@ int stixels_output_bytes(const stixels_handle *h, int32_t width, int32_t height,
 int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, int32_t height,
                     void *stream, const stixels_output *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * stixels_compute through the fused persistent kernel with its workspace in
+ * a fixed device array of the library (64 MiB per GPU, held from the first
+ * stixels_create on that GPU until the process ends) instead of the
+ * handle's workspace, so it also runs on STIXELS_FLAG_BATCH_ONLY handles.
+ * Arguments and output as stixels_compute; the handle's camera pose only.
+ * The handle's device must be current.  Frames whose descriptor, task list
+ * and one scratch slot of (4 + bins)(height + 1) floats exceed the array
+ * return STIXELS_E_RANGE (no valid handle reaches that); a frame with more
+ * columns than the array has slots runs on fewer workgroups.  Allocates
+ * nothing.  Every call on one GPU shares that GPU's array, so calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and
+ * must be ordered by the caller. */
+int stixels_compute_noalloc(stixels_handle *h, const float *d_disparity, int32_t width,
+                            int32_t height, void *stream, const stixels_output *out);
+
 /* stixels_compute for a frame with its own camera pose (see stixels_pose):
  * the frame's ground table and thresholds are built on the device into the
  * handle's pose area, on `stream`, ahead of the frame's kernels.  Same

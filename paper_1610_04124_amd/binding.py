@@ -36,7 +36,7 @@ EXPORTS = (
     "stixels_compute_batch", "stixels_debug_tables", "stixels_set_frame_path",
     "stixels_get_frame_path", "stixels_device_bytes", "stixels_batch_device_bytes",
     "stixels_debug_stage_times", "stixels_compute_pose", "stixels_debug_pose_tables",
-    "stixels_set_object_lut",
+    "stixels_set_object_lut", "stixels_compute_noalloc",
 )
 
 
@@ -124,6 +124,7 @@ def lib():
         L.stixels_output_capacity.argtypes = [vp, i32, P(i32)]
         L.stixels_compute.argtypes = [vp, vp, i32, i32, vp, P(Output)]
         L.stixels_compute_pose.argtypes = [vp, vp, i32, i32, P(Pose), vp, P(Output)]
+        L.stixels_compute_noalloc.argtypes = [vp, vp, i32, i32, vp, P(Output)]
         L.stixels_debug_pose_tables.argtypes = [vp, P(Pose), i32, vp, C.c_size_t, vp]
         L.stixels_last_error.argtypes = [vp]
         L.stixels_last_error.restype = C.c_char_p
@@ -370,6 +371,21 @@ class Stixels:
                                             C.byref(ps), _stream_ptr(stream), C.byref(o))
         if rc != OK:
             self._err(rc, "stixels_compute" if pose is None else "stixels_compute_pose")
+        return out
+
+    def compute_noalloc(self, disp, out: FrameOutput, stream=None) -> FrameOutput:
+        """Enqueue one device frame through stixels_compute_noalloc (the fused
+        kernel with the library's fixed per-GPU workspace; the caller brings
+        the output, and calls that overlap on one GPU race)."""
+        import torch
+        _check_device_tensor(disp, torch.float32, "disparity")
+        H, W = disp.shape
+        self.check_output(out, W, disp.device)
+        o = out.struct()
+        rc = lib().stixels_compute_noalloc(self.h, C.c_void_p(disp.data_ptr()), int(W), int(H),
+                                           _stream_ptr(stream), C.byref(o))
+        if rc != OK:
+            self._err(rc, "stixels_compute_noalloc")
         return out
 
     def debug_pose_tables(self, pose, height: int, stream=None):

@@ -12,6 +12,7 @@
 #include "handle.h"
 #include "job_desc.h"
 #include "launch.h"
+#include "noalloc.h"
 #include "stixels.h"
 
 using namespace stx;
@@ -255,6 +256,9 @@ int stixels_create(const stixels_params* params, stixels_handle** out) {
     rc = build_tables(h);
     if (rc == STIXELS_OK && hipGetDevice(&h->device) != hipSuccess)
         rc = fail(h, STIXELS_E_HIP, "no HIP device");
+    // the fixed workspace of stixels_compute_noalloc on this device (once per
+    // device; that entry point reports a failure here when it is called)
+    if (rc == STIXELS_OK) (void)noalloc_setup(h->device);
     if (rc == STIXELS_OK &&
         hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
             hipSuccess)

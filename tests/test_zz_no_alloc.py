@@ -1,0 +1,129 @@
+"""stixels_compute_noalloc (the fused kernel with the library's fixed per-GPU
+workspace) against stixels_compute on the same frames, bit for bit: two calls
+in a row, the second with a smaller frame; a batch-only handle; frames with
+more columns than the fixed workspace has scratch slots; costs off the grid;
+and the size limit, which is checked on the host before any launch."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_1610_04124_amd as P
+from paper_1610_04124_amd import binding as B
+from gpu_helpers import announce, assert_frames_equal, device, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def poisoned_output(h, W, H):
+    """An output whose every byte holds a non-result value, so that a column
+    the call did not write shows up as a mismatch."""
+    out = P.FrameOutput(h.num_columns(W), h.capacity(H), device())
+    out.counts.fill_(-7)
+    out.records.fill_(-1)
+    out.total.fill_(-3.0)
+    out.overflow.fill_(9)
+    return out
+
+
+def raw(out):
+    """Every byte of the four output arrays (unused records included)."""
+    return {k: getattr(out, k).cpu().numpy().view(np.uint8)
+            for k in ("counts", "records", "total", "overflow")}
+
+
+def noalloc_frame(h, disp):
+    import torch
+    H, W = disp.shape
+    out = poisoned_output(h, W, H)
+    h.compute_noalloc(to_device(disp), out)
+    torch.cuda.synchronize()
+    return out
+
+
+def compute_frame(h, disp, path):
+    import torch
+    H, W = disp.shape
+    h.set_frame_path(path)
+    out = poisoned_output(h, W, H)
+    h.compute(to_device(disp), out)
+    torch.cuda.synchronize()
+    h.set_frame_path(0)
+    return out
+
+
+def assert_same(a, b, label):
+    ra, rb = raw(a), raw(b)
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), (label, k)
+
+
+def frame(W, H, D, seed):
+    return synth.generate_frame(synth.SceneSpec(W, H, D, synth.camera_for_size(W, H), seed=seed))
+
+
+def test_two_calls_second_smaller_equal_compute_and_oracle():
+    p = synth.make_params(max_width=1024, max_height=440)
+    h = P.Stixels(p)
+    big = frame(1024, 440, 128, 3)
+    small = synth.generate_frame(synth.SceneSpec(640, 240, 128, synth.camera_for_size(1024, 440),
+                                                 seed=4))
+    announce("noalloc 1024x440 then 640x240")
+    got = [noalloc_frame(h, big), noalloc_frame(h, small)]
+    for d, g, label in zip((big, small), got, ("1024x440", "640x240")):
+        # the staged kernels: every stixel, count, total and flag; the fused
+        # kernel (the one this entry point launches): every byte
+        assert_frames_equal(g.to_host(), compute_frame(h, d, 1).to_host(), f"{label} staged")
+        assert_same(g, compute_frame(h, d, 2), f"{label} fused")
+    assert_frames_equal(got[1].to_host(), oracle.frame(p, small), "640x240 oracle")
+    h.close()
+
+
+def test_batch_only_handle_and_fewer_slots_than_columns():
+    # 2048x880, 256 disparities, s = 3: 682 columns, while the fixed
+    # workspace holds 73 scratch slots of (4 + 256)(881) floats
+    W, H, D = 2048, 880, 256
+    kw = dict(camera=synth.camera_for_size(W, H), stixel_width=3, max_disparity=D, max_width=W,
+              max_height=H)
+    ref_h = P.Stixels(synth.make_params(**kw))
+    h = P.Stixels(synth.make_params(flags=B.FLAG_BATCH_ONLY, **kw))
+    first, second = frame(W, H, D, 7), frame(1536, 600, D, 8)
+    announce("noalloc batch-only 2048x880 s3 then 1536x600")
+    g1, g2 = noalloc_frame(h, first), noalloc_frame(h, second)
+    assert_frames_equal(g1.to_host(), compute_frame(ref_h, first, 1).to_host(), "2048x880")
+    assert_frames_equal(g2.to_host(), compute_frame(ref_h, second, 1).to_host(), "1536x600")
+    assert_same(g2, compute_frame(ref_h, second, 2), "1536x600 fused")
+    h.close()
+    ref_h.close()
+
+
+def test_off_grid_costs_equal_compute():
+    p = synth.make_params(max_width=640, max_height=240, cost_grid_log2=-1)
+    h = P.Stixels(p)
+    a = frame(640, 240, 128, 11)
+    b = synth.generate_frame(synth.SceneSpec(320, 120, 128, synth.camera_for_size(640, 240),
+                                             seed=12))
+    announce("noalloc off-grid 640x240 then 320x120")
+    ga, gb = noalloc_frame(h, a), noalloc_frame(h, b)
+    assert_same(ga, compute_frame(h, a, 2), "off-grid 640x240")
+    assert_same(gb, compute_frame(h, b, 2), "off-grid 320x120")
+    h.close()
+
+
+def test_frame_beyond_the_fixed_workspace_is_rejected():
+    # s = 1 and one row: 9e6 columns need a 72 MB task list, more than the
+    # 64 MiB workspace holds; rejected on the host before any launch
+    import torch
+    W = 9_000_000
+    h = P.Stixels(synth.make_params(stixel_width=1, max_width=W, max_height=1,
+                                    flags=B.FLAG_BATCH_ONLY))
+    disp = torch.zeros((1, W), dtype=torch.float32, device=device())
+    out = poisoned_output(h, W, 1)
+    announce("noalloc size limit")
+    with pytest.raises(B.StixelsError) as ei:
+        h.compute_noalloc(disp, out)
+    assert ei.value.code == B.E_RANGE
+    torch.cuda.synchronize()
+    assert int(out.counts.min()) == -7 and int(out.counts.max()) == -7
+    h.close()
