@@ -525,14 +525,29 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
     // and the object-cost row are vector memory instructions of a step.
     constexpr bool QB = (S <= 8);                    // the pixel a slot at a time
     constexpr bool BLK = BLOCKS && QB;               // and the other four
+    // PIPE: one-wave columns of up to 8 slots gather a step's object
+    // prefixes one step early.  The gathers of step j (stixels starting at
+    // b = j+1) depend only on row j's prefix values, never on a cost, so
+    // step j issues them for step j+1 right after folding its own, and a
+    // whole step of work covers their latency.  The slot also holds the
+    // prefix values of row j+1 of each of its steps.
+    constexpr bool PIPE = (W == 1) && QB;
     struct Blk {
         int q = 0, thi = 0, tlo = 0;
         float ps = 0.0f, pg = 0.0f;
+        float na = 0.0f, nn = 0.0f;     // PA and PN2 at j+2 (PIPE)
     };
+    const auto par = make_rsrc(in.PA, stride4);
+    const auto pnr = make_rsrc(in.PN2, stride4);
     auto load_block = [&](int sj) {
         Blk k;
         const int j = 64 * sj + lane;
         k.q = (j + 1 < H) ? (int)in.q[j + 1] : -1;
+        if constexpr (PIPE) {
+            const int kk = min(j + 2, H);
+            k.na = buf_load(par, kk);
+            k.nn = buf_load(pnr, kk);
+        }
         if constexpr (BLK) {
             k.ps = buf_load(psr, j + 1);              // past the table: 0, never used
             k.pg = buf_load(pgr, j + 1);
@@ -568,6 +583,20 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 #pragma unroll
     for (int c = 0; c < NCH; ++c) pcol[c] = orow[c] = 0.0f;
     if (H > 1) load_next(0, __builtin_amdgcn_readfirstlane((int)in.q[0]));
+
+    // PIPE: the object prefix gathers of step 0 (base b = 1; row 0's prefix
+    // values are lane 0 of slot 0)
+    float pkP[PIPE ? SW : 1];
+    int fSP[PIPE ? SW : 1];
+    if constexpr (PIPE) {
+        const float nA0 = readlane_f(eA[0], 0), nN0 = readlane_f(eN[0], 0);
+#pragma unroll
+        for (int t = 0; t < SW; ++t) {
+            const uint32_t fi = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, cmean);
+            pkP[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(t * 256));
+            fSP[t] = (int)fi;
+        }
+    }
 
     // The ground and sky data terms of a stixel [b, k] are prefix
     // differences whose b-side does not depend on k, and their priors depend
@@ -605,8 +634,10 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
                 if (t == tj) {
                     Co = readlane_f(mO[t], jl);
                     fp = readlane_i(fO[t], jl);
-                    bA = readlane_f(eA[t], jl);
-                    bN = readlane_f(eN[t], jl);
+                    if constexpr (!PIPE) {
+                        bA = readlane_f(eA[t], jl);
+                        bN = readlane_f(eN[t], jl);
+                    }
                 }
             }
         };
@@ -644,7 +675,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
         // index is masked): skipping them one by one would cost more than
         // the work.  Groups bound the registers a tall column holds.
         constexpr int G = (SW <= 8) ? SW : 4;
-        constexpr bool EARLY = (NCH == 2) && (S <= 8);
+        constexpr bool EARLY = (NCH == 2) && (S <= 8) && !PIPE;
         float pk[SW];
         int fS[SW];
         auto gather = [&](int g0) {
@@ -748,7 +779,32 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
             qtab[64 * c + lane] = pr - pcol[c];
         }
 
-        if constexpr (EARLY) {
+        if constexpr (PIPE) {
+            // fold the gathers issued a step ago, then issue the next
+            // step's (base b+1: row j+1's prefix values); a slot that closes
+            // with this step still gathers once, into rows never folded
+            const float nA = readlane_f(blk.na, jl), nN = readlane_f(blk.nn, jl);
+            float qv[SW];
+#pragma unroll
+            for (int t = 0; t < SW; ++t) {
+                if (t < sj) continue;
+                qv[t] = qtab[(uint32_t)fSP[t] & (64u * NCH - 1u)];
+            }
+#pragma unroll
+            for (int t = 0; t < SW; ++t) {
+                if (t < sj) continue;
+                const bool act = (t > sj) || (lane > jl);          // rows k > j only
+                float cO = qv[t] + pkP[t];
+                cO = act ? cO : INF;
+                const bool better = cO < mO[t];
+                mO[t] = better ? cO : mO[t];
+                fO[t] = better ? fSP[t] : fO[t];
+                if constexpr (LINKS) bO[t] = better ? b : bO[t];
+                const uint32_t fi = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, cmean);
+                pkP[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(t * 256));
+                fSP[t] = (int)fi;
+            }
+        } else if constexpr (EARLY) {
             if (group_open(0)) fold(0);
         } else {
 #pragma unroll
