@@ -1,4 +1,5 @@
-"""Build step of the CPU oracle: plain gcc, FP64, no fast-math, OpenMP over columns."""
+"""Build step of the CPU oracles (stixels and the semi-global matching stage):
+plain gcc, FP64, no fast-math, OpenMP over columns."""
 
 from __future__ import annotations
 
@@ -10,12 +11,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 def build_oracle(force: bool = True) -> str:
     out = os.path.join(_HERE, "libstixel_oracle.so")
-    src = os.path.join(_HERE, "stixel_oracle.c")
+    srcs = [os.path.join(_HERE, "stixel_oracle.c"), os.path.join(_HERE, "sgm_oracle.c")]
     if not force and os.path.exists(out):
         return out
     tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-Wall", "-Wextra", "-fPIC",
-           "-shared", "-fopenmp", src, "-o", tmp, "-lm"]
+           "-shared", "-fopenmp", *srcs, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
