@@ -299,7 +299,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
 // prefix tables at ws (PG, PS, PA, PN at 0..3 (h+1), the object rows from
 // po_at floats on).  Returns the column's disparity range [fmin, fmax].
 template <int S>
-__device__ void column_tables(const JobDesc& J, const int col, const bool exists, int16_t* qs,
+__device__ __forceinline__ void column_tables(const JobDesc& J, const int col, const bool exists, int16_t* qs,
                               float* ws, const int po_at, int& fmin_out, int& fmax_out) {
     const int lane = threadIdx.x & 63;
     const int H = J.H, D = J.D, stride = H + 1;

@@ -109,7 +109,7 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
 // row's final object, ground and sky cost and best object mean are in LDS
 // (L.crow_*), its prefix values in the column's tables (in).
 template <int S, class Lds>
-__device__ void backtrack_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
+__device__ __forceinline__ void backtrack_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                                  const ColumnOut& out, const Lds& L) {
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
@@ -303,7 +303,7 @@ __device__ void backtrack_column(const int H, const int vtop, const Prior P, con
 // prefixes (2q+1 and 2 per valid pixel), so that prefix cancellation does
 // not enter the reported cost, and its prior is added from the constants.
 template <int S, class Lds>
-__device__ void backtrack_links(const int H, const int vtop, const Prior P, const ColumnIn& in,
+__device__ __forceinline__ void backtrack_links(const int H, const int vtop, const Prior P, const ColumnIn& in,
                                 const ColumnOut& out, const Lds& L) {
     const int lane = threadIdx.x & 63;
     const int fbase = in.fbase;
@@ -431,7 +431,7 @@ __device__ void backtrack_links(const int H, const int vtop, const Prior P, cons
 // per class (one select per candidate) and backtrack along those links, for
 // costs off the grid.  On return the results are written.
 template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false>
-__device__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
+__device__ __forceinline__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                              const ColumnOut& out, ColumnLds<S, W, 64 * NCH, LINKS>& L,
                              const float* po_lds = nullptr) {
     static_assert(W == 1 || W == 2 || W == 4, "waves per column");
@@ -906,7 +906,7 @@ __device__ void solve_column(const int H, const int vtop, const Prior P, const C
 // the last pair's second half idle; its results are not written).
 // qs2: the two columns' reduced pixels in LDS, [2][64 S].
 template <int S, int NCH>
-__device__ void solve_pair(const int H, const int vtop, const Prior P, const ColumnIn& in0,
+__device__ __forceinline__ void solve_pair(const int H, const int vtop, const Prior P, const ColumnIn& in0,
                            const ColumnIn& in1, const ColumnOut& out0, const ColumnOut& out1,
                            const bool has1, const int16_t* qs2, float* qtab2,
                            ColumnLds<S, 1>& L) {
