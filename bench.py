@@ -6,8 +6,9 @@ three-class recurrence and backtracking) over one batch of 64 synthetic
 persistent batched launch replayed from a HIP graph.  Beside it: the plain
 per-frame path (three staged kernels, and one fused launch) with per-frame
 latency percentiles and the HBM fraction of its reduction and table kernels;
-the 2048x880 batches; the 256-frame uneven batch; serving of 8 camera streams
-for 60 s; the CPU oracle on the host cores.
+the 2048x880 batches; the 256-frame uneven batch; 64 stereo pairs through
+the semi-global matching stage and on into stixels; serving of 8 camera
+streams for 60 s; the CPU oracle on the host cores.
 
 Prints one JSON line.  Roofline of the dominant kernel (the persistent
 kernel): algorithmic work = 13 VALU lane-ops per (cut, row) pair of the
@@ -261,6 +262,78 @@ def uneven(warmup, steps, tune_launch=True):
     return res
 
 
+def sgm_bytes_per_frame(W=W, H=H, D=D_RANGE):
+    """Algorithmic HBM bytes of the matching stage per frame: census (both
+    images read, both word arrays written), each of the four path passes
+    reading both word arrays once, the summed costs written (first pass),
+    read and written (two passes) and read (last pass), the map written."""
+    n = W * H
+    return 2 * n + 16 * n + 4 * 16 * n + 2 * n * D * (1 + 2 + 2 + 1) + 4 * n
+
+
+def stereo(warmup, steps, tune_launch=True):
+    """64 rectified stereo pairs of the headline scenes (1024x440, 128
+    disparities): the semi-global matching stage alone, and stereo pairs to
+    stixels (matching, then the batched stixel launch on its maps, replayed
+    from a HIP graph)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from synth.stereo import StereoSpec, generate_stereo
+    import paper_1610_04124_amd as P
+
+    dev = torch.device("cuda", 0)
+    pairs = [generate_stereo(StereoSpec(synth.SceneSpec(seed=i))) for i in range(FRAMES)]
+    L = torch.from_numpy(np.stack([p[0] for p in pairs])).to(dev)
+    R = torch.from_numpy(np.stack([p[1] for p in pairs])).to(dev)
+    truth = np.stack([p[2] for p in pairs])
+    m = P.Sgm(W, H, D_RANGE, max_frames=FRAMES)
+    disp = torch.empty((FRAMES, H, W), dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream()
+    for _ in range(warmup):
+        m.compute(L, R, disp, stream)
+    torch.cuda.synchronize()
+    seen = truth >= 0
+    got = disp.cpu().numpy()
+    accuracy = float(((got == truth) & seen).sum() / seen.sum())
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
+    for i in range(steps):
+        ev[2 * i].record(stream)
+        m.compute(L, R, disp, stream)
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    sgm_ms = [ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)]
+    sgm_s = statistics.mean(sgm_ms) * 1e-3
+    bytes_frame = sgm_bytes_per_frame()
+
+    h = P.Stixels(synth.make_params(flags=P.binding.FLAG_BATCH_ONLY))
+    outs = [h.new_output(W, H) for _ in range(FRAMES)]
+    b = P.Batch(FRAMES, FRAMES * (W // S_WIDTH), H, D_RANGE)
+    tuned_capture(b, list(zip([h] * FRAMES, [disp[i] for i in range(FRAMES)], outs)), stream,
+                  tune_launch)
+    for _ in range(warmup):
+        m.compute(L, R, disp, stream)
+        b.replay(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        m.compute(L, R, disp, stream)
+        b.replay(stream)
+    torch.cuda.synchronize()
+    both = (time.perf_counter() - t0) / steps
+    return {"sgm_fps": round(FRAMES / sgm_s, 2), "sgm_ms_per_batch": round(sgm_s * 1e3, 4),
+            "stereo_to_stixels_fps": round(FRAMES / both, 2),
+            "stereo_to_stixels_ms_per_batch": round(both * 1e3, 4),
+            "sgm_roofline": {"bound": "hbm", "bytes_per_frame": bytes_frame,
+                             "achieved_GBps": round(bytes_frame * FRAMES / sgm_s / 1e9, 1),
+                             "peak_GBps": HBM_PEAK / 1e9,
+                             "frac": round(bytes_frame * FRAMES / sgm_s / HBM_PEAK, 4)},
+            "disparity_equal_to_scene": round(accuracy, 4),
+            "frames": FRAMES, "max_disparity": D_RANGE, "paths": 4, "p1": 10, "p2": 120,
+            "census": "9x7", "workspace_bytes": m.device_bytes()}
+
+
 def per_frame_legs(h, d_frames, outs, stream, steps, latency_frames, tune_launch):
     """The per-frame paths: three staged kernels and one fused launch.  Per
     path: throughput with frames back to back, and latency per frame (HIP
@@ -408,6 +481,7 @@ def profile_mode(args):
     uneven  the 256-frame uneven batch;
     frame   the staged per-frame path (three kernels) on the 64 frames;
     fused   the fused per-frame path (one launch per frame) on the 64 frames;
+    sgm     the semi-global matching stage over 64 stereo pairs 1024x440;
     copy    a plain 256 MiB device-to-device copy, whose FETCH_SIZE and
             WRITE_SIZE readings calibrate the HBM byte counters."""
     import torch
@@ -427,6 +501,19 @@ def profile_mode(args):
     import paper_1610_04124_amd as P
 
     stream = torch.cuda.Stream()
+    if args.profile_mode == "sgm":
+        import numpy as np
+        from synth.stereo import StereoSpec, generate_stereo
+        pairs = [generate_stereo(StereoSpec(synth.SceneSpec(seed=i))) for i in range(FRAMES)]
+        L = torch.from_numpy(np.stack([p[0] for p in pairs])).to(dev)
+        R = torch.from_numpy(np.stack([p[1] for p in pairs])).to(dev)
+        m = P.Sgm(W, H, D_RANGE, max_frames=FRAMES)
+        disp = torch.empty((FRAMES, H, W), dtype=torch.float32, device=dev)
+        for _ in range(args.launches):
+            m.compute(L, R, disp, stream)
+        torch.cuda.synchronize()
+        print(f"sgm: {args.launches} launches over {FRAMES} stereo pairs", flush=True)
+        return
     if args.profile_mode == "uneven":
         items, _ = uneven_items(dev)
         ntasks = sum(h.num_columns(d.shape[1]) for h, d, _ in items)
@@ -480,7 +567,8 @@ def main():
     ap.add_argument("--latency-frames", type=int, default=200)
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--profile-mode", choices=["batch", "hires", "uneven", "frame", "fused", "copy"])
+    ap.add_argument("--profile-mode", choices=["batch", "hires", "uneven", "frame", "fused", "copy",
+                                               "sgm"])
     ap.add_argument("--launches", type=int, default=3)
     ap.add_argument("--waves", type=int, default=0,
                     help="profile modes: waves per column (0: automatic per frame, one batched)")
@@ -571,6 +659,8 @@ def main():
                                                  tune_launch)
     result["uneven256"] = uneven(args.warmup, max(3, args.steps // 5), tune_launch)
     print("[bench] hires, mean and uneven legs done", file=sys.stderr, flush=True)
+    result["stereo64_1024x440"] = stereo(args.warmup, max(3, args.steps // 5), tune_launch)
+    print("[bench] stereo leg done", file=sys.stderr, flush=True)
     if args.serve_seconds > 0:
         result["serving"] = serve(args.serve_seconds)
         print("[bench] serving at 30 Hz done", file=sys.stderr, flush=True)

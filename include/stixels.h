@@ -429,6 +429,69 @@ int stixels_debug_stage_times(stixels_handle *h, const float *d_disparity, int32
  * writes the number of mismatches to *host_mismatches.  Synchronous. */
 int stixels_selftest_mean(int32_t d_range, int32_t max_height, int64_t *host_mismatches);
 
+/* ------------------------------------------------------------------ stereo
+ * Semi-global matching ahead of the stixel path.  The paper takes its
+ * disparity maps from a GPU semi-global matching with census costs (Sec. 1,
+ * Sec. 5) and leaves that stage out of its timings; this stage produces the
+ * same kind of map on the device from a rectified stereo pair:
+ *   census   9 x 7 window; bit i of a pixel's 62-bit word is 1 iff the i-th
+ *            neighbour (row-major, centre skipped) lies inside the image and
+ *            is darker than the centre
+ *   cost     C(p, d) = Hamming distance of the left word at (y, x) and the
+ *            right word at (y, x - d); 62 where x - d < 0
+ *   paths    for the four axis directions r: L_r(p, d) = C(p, d) +
+ *            min(L_r(p-r, d), L_r(p-r, d -+ 1) + p1, M + p2) - M with
+ *            M = min_k L_r(p-r, k); L_r = C at a path's first pixel
+ *   select   d_L = the smallest d minimising the summed cost S(p, d);
+ *            d_R(y, x) = the smallest d minimising S((y, x + d), d)
+ *   check    the output is d_L where x - d_L >= 0 and
+ *            |d_L - d_R(y, x - d_L)| <= 1, else -1 (invalid)
+ * All arithmetic is integer. */
+typedef struct stixels_sgm stixels_sgm;
+
+typedef struct {
+    int32_t max_width, max_height;  /* largest frame; max_width <= 8192 (LDS of a row) */
+    int32_t max_disparity;          /* disparities 0..max_disparity-1: a multiple of 4 in 4..256 */
+    int32_t p1, p2;                 /* path penalties, 0 <= p1 <= p2 <= 1000 */
+    int32_t paths;                  /* 4 */
+    int32_t max_frames;             /* frames per stixels_sgm_compute call */
+} stixels_sgm_params;
+
+/* Validate, and allocate the workspace: both views' census words and the
+ * summed costs, uint16 [max_frames][max_height][max_width][max_disparity]
+ * (device bytes: stixels_sgm_device_bytes).  STIXELS_E_INVALID_ARG with the
+ * reason in stixels_sgm_last_error(NULL), or STIXELS_E_NOMEM. */
+int stixels_sgm_create(const stixels_sgm_params *params, stixels_sgm **out);
+int stixels_sgm_destroy(stixels_sgm *m);
+const char *stixels_sgm_last_error(const stixels_sgm *m);
+int stixels_sgm_device_bytes(const stixels_sgm *m, size_t *bytes);
+
+/* Disparity of `frames` stereo pairs stored back to back: d_left and
+ * d_right device uint8 [frames][height][width] (row-major, row 0 at the
+ * top), d_disparity device float32 [frames][height][width], caller-owned.
+ * Asynchronous on `stream`; allocates nothing; calls on one handle must not
+ * overlap (they share its workspace).  STIXELS_E_INVALID_ARG for null
+ * pointers, sizes beyond the handle's or frames outside 1..max_frames. */
+int stixels_sgm_compute(stixels_sgm *m, const uint8_t *d_left, const uint8_t *d_right,
+                        int32_t width, int32_t height, int32_t frames, void *stream,
+                        float *d_disparity);
+
+/* Host copy of an intermediate of frame 0 of the last stixels_sgm_compute
+ * (synchronises the device): which 0 = left census words, 1 = right census
+ * words (uint64 [height][width]), 2 = the cost volume as the last pass finds
+ * it (uint16 [height][width][max_disparity]): the sum of the top-to-bottom,
+ * bottom-to-top and right-to-left path terms; the left-to-right pass, which
+ * selects, adds its own term in registers and does not write it back. */
+int stixels_sgm_debug(const stixels_sgm *m, int32_t which, void *host_dst, size_t bytes);
+
+/* A stereo pair in, stixels out: stixels_sgm_compute of one frame into
+ * d_disparity (caller-owned device float32 [height][width], which keeps the
+ * map), then stixels_compute on it, both on `stream`.  The two handles must
+ * share max_disparity (whole-pixel bins). */
+int stixels_compute_stereo(stixels_handle *h, stixels_sgm *m, const uint8_t *d_left,
+                           const uint8_t *d_right, int32_t width, int32_t height, void *stream,
+                           float *d_disparity, const stixels_output *out);
+
 #ifdef __cplusplus
 }
 #endif

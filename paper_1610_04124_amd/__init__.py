@@ -9,6 +9,7 @@ from .binding import (  # noqa: F401
     EXPORTS,
     Batch,
     FrameOutput,
+    Sgm,
     Stixels,
     StixelsError,
     compute_batch,
@@ -19,5 +20,5 @@ from .binding import (  # noqa: F401
     status_string,
 )
 
-__all__ = ["Batch", "Stixels", "FrameOutput", "StixelsError", "compute_batch", "decode_records",
+__all__ = ["Batch", "Sgm", "Stixels", "FrameOutput", "StixelsError", "compute_batch", "decode_records",
            "host_table", "lib", "selftest_mean", "status_string", "EXPORTS"]

@@ -37,6 +37,9 @@ EXPORTS = (
     "stixels_get_frame_path", "stixels_device_bytes", "stixels_batch_device_bytes",
     "stixels_debug_stage_times", "stixels_compute_pose", "stixels_debug_pose_tables",
     "stixels_set_object_lut", "stixels_compute_noalloc",
+    "stixels_sgm_create", "stixels_sgm_destroy", "stixels_sgm_last_error",
+    "stixels_sgm_device_bytes", "stixels_sgm_compute", "stixels_sgm_debug",
+    "stixels_compute_stereo",
 )
 
 
@@ -91,6 +94,15 @@ class BatchConfig(C.Structure):
 
 
 BATCH_POSES = 1
+
+
+class SgmParams(C.Structure):
+    _fields_ = [("max_width", C.c_int32), ("max_height", C.c_int32),
+                ("max_disparity", C.c_int32), ("p1", C.c_int32), ("p2", C.c_int32),
+                ("paths", C.c_int32), ("max_frames", C.c_int32)]
+
+
+SGM_LEFT_CENSUS, SGM_RIGHT_CENSUS, SGM_COSTS = range(3)
 
 
 def to_pose(pose) -> Pose:
@@ -160,6 +172,14 @@ def lib():
                                                 P(C.c_float)]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
+        L.stixels_sgm_create.argtypes = [P(SgmParams), P(vp)]
+        L.stixels_sgm_destroy.argtypes = [vp]
+        L.stixels_sgm_last_error.argtypes = [vp]
+        L.stixels_sgm_last_error.restype = C.c_char_p
+        L.stixels_sgm_device_bytes.argtypes = [vp, P(C.c_size_t)]
+        L.stixels_sgm_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp]
+        L.stixels_sgm_debug.argtypes = [vp, i32, vp, C.c_size_t]
+        L.stixels_compute_stereo.argtypes = [vp, vp, vp, vp, i32, i32, vp, vp, P(Output)]
         _lib = L
     return _lib
 
@@ -387,6 +407,34 @@ class Stixels:
         if rc != OK:
             self._err(rc, "stixels_compute_noalloc")
         return out
+
+    def compute_stereo(self, sgm: "Sgm", left, right, out: FrameOutput | None = None,
+                       disparity=None, stream=None):
+        """A device stereo pair (uint8 [height, width] each) through the
+        matching stage and this handle's stixel path on one stream
+        (stixels_compute_stereo).  Returns (stixels, disparity map)."""
+        import torch
+        _check_device_tensor(left, torch.uint8, "left image")
+        _check_device_tensor(right, torch.uint8, "right image")
+        if left.shape != right.shape or left.dim() != 2:
+            raise StixelsError(E_INVALID_ARG, "left and right must be equal 2-D images")
+        H, W = left.shape
+        if out is None:
+            out = self.new_output(W, H, left.device)
+        self.check_output(out, W, left.device)
+        if disparity is None:
+            disparity = torch.empty((H, W), dtype=torch.float32, device=left.device)
+        _check_device_tensor(disparity, torch.float32, "disparity")
+        if tuple(disparity.shape) != (H, W):
+            raise StixelsError(E_INVALID_ARG, "disparity map must match the images")
+        o = out.struct()
+        rc = lib().stixels_compute_stereo(self.h, sgm.h, C.c_void_p(left.data_ptr()),
+                                          C.c_void_p(right.data_ptr()), int(W), int(H),
+                                          _stream_ptr(stream), C.c_void_p(disparity.data_ptr()),
+                                          C.byref(o))
+        if rc != OK:
+            self._err(rc, "stixels_compute_stereo")
+        return out, disparity
 
     def debug_pose_tables(self, pose, height: int, stream=None):
         """The ground table [height][D] and diving / gravity thresholds
@@ -633,3 +681,74 @@ class Batch:
         if rc != OK:
             self._err(rc, "stixels_batch_info")
         return g.value, t.value
+
+
+class Sgm:
+    """Semi-global matching stage ahead of the stixel path (stixels_sgm_* in
+    include/stixels.h): census 9x7 costs, four path directions, left-right
+    check.  Argument marshalling only."""
+
+    def __init__(self, max_width: int, max_height: int, max_disparity: int, p1: int = 10,
+                 p2: int = 120, paths: int = 4, max_frames: int = 1):
+        sp = SgmParams(int(max_width), int(max_height), int(max_disparity), int(p1), int(p2),
+                       int(paths), int(max_frames))
+        h = C.c_void_p()
+        rc = lib().stixels_sgm_create(C.byref(sp), C.byref(h))
+        if rc != OK:
+            raise StixelsError(rc, "stixels_sgm_create: " + lib().stixels_sgm_last_error(None).decode())
+        self.h = h
+        self.D = int(max_disparity)
+        self.max_frames = int(max_frames)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().stixels_sgm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t()
+        rc = lib().stixels_sgm_device_bytes(self.h, C.byref(b))
+        if rc != OK:
+            raise StixelsError(rc, "stixels_sgm_device_bytes")
+        return int(b.value)
+
+    def compute(self, left, right, disparity=None, stream=None):
+        """Enqueue the disparity of device stereo pairs: uint8 [H, W] or
+        [n, H, W] each; returns the float32 map(s) of the same shape (-1
+        where the left-right check fails)."""
+        import torch
+        _check_device_tensor(left, torch.uint8, "left image")
+        _check_device_tensor(right, torch.uint8, "right image")
+        if left.shape != right.shape or left.dim() not in (2, 3):
+            raise StixelsError(E_INVALID_ARG, "left and right must be equal [H, W] or [n, H, W]")
+        n = 1 if left.dim() == 2 else int(left.shape[0])
+        H, W = int(left.shape[-2]), int(left.shape[-1])
+        if disparity is None:
+            disparity = torch.empty(tuple(left.shape), dtype=torch.float32, device=left.device)
+        _check_device_tensor(disparity, torch.float32, "disparity")
+        if tuple(disparity.shape) != tuple(left.shape) or disparity.device != left.device:
+            raise StixelsError(E_INVALID_ARG, "disparity must match the images")
+        rc = lib().stixels_sgm_compute(self.h, C.c_void_p(left.data_ptr()),
+                                       C.c_void_p(right.data_ptr()), W, H, n,
+                                       _stream_ptr(stream), C.c_void_p(disparity.data_ptr()))
+        if rc != OK:
+            raise StixelsError(rc, "stixels_sgm_compute: " + lib().stixels_sgm_last_error(self.h).decode())
+        return disparity
+
+    def debug(self, which: int, width: int, height: int) -> np.ndarray:
+        """Census words (which 0 left, 1 right) or summed costs (2) of frame 0
+        of the last compute, as host arrays (synchronises)."""
+        if which == SGM_COSTS:
+            a = np.zeros((height, width, self.D), np.uint16)
+        else:
+            a = np.zeros((height, width), np.uint64)
+        rc = lib().stixels_sgm_debug(self.h, int(which), a.ctypes.data, a.nbytes)
+        if rc != OK:
+            raise StixelsError(rc, "stixels_sgm_debug")
+        return a

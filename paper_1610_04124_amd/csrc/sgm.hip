@@ -1,0 +1,458 @@
+// sgm.hip -- semi-global matching on gfx950: the stereo stage whose
+// disparity maps feed the stixel path.  The paper takes its disparity from a
+// GPU semi-global matching with census costs (Sec. 1, Sec. 5) and excludes
+// that stage from its own timings; here it runs on the device ahead of the
+// stixel kernels, so a stereo pair goes in and stixels come out with no host
+// round trip.
+//
+// Method (Hirschmuller's semi-global matching, census costs):
+//   census   9 x 7 window, bit i = 1 iff neighbour i (row-major, centre
+//            skipped) lies inside the image and is darker than the centre
+//   cost     C(p, d) = Hamming distance of left census (y, x) and right
+//            census (y, x - d); 62 when x - d < 0
+//   paths    L_r(p, d) = C(p, d) + min(L_r(p-r, d), L_r(p-r, d -+ 1) + P1,
+//            M + P2) - M, M = min_k L_r(p-r, k); L_r = C at a path's start
+//   select   d_L = smallest d of minimum summed cost; d_R(y, x) = smallest d
+//            minimising S((y, x + d), d); left-right check |d_L - d_R| <= 1,
+//            else -1 (the stixel input's invalid value)
+//
+// Work distribution: one wave64 per path line (an image row for the two
+// horizontal directions, a column for the two vertical ones), lanes over
+// disparities (lane l owns DPL consecutive disparities l DPL + i), steps
+// along the line.  A step's neighbour terms d -+ 1 cross lanes by one DPP
+// wavefront shift each; M is a DPP row minimum and three scalar minima.  The
+// summed costs S live in HBM as uint16 [frame][y][x][d]: the top-to-bottom
+// pass writes them, the bottom-to-top and right-to-left passes add to them,
+// and the left-to-right pass, run last, adds its own term in registers and
+// selects d_L (wave minimum of cost * 256 + d), keeps the right view's
+// minima per target column in LDS (lane d of step x updates column x - d)
+// and applies the left-right check once its row is done; S is never written
+// back by that pass.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "handle.h"
+#include "sgm.h"
+#include "stixels.h"
+
+namespace stx::sgm {
+
+namespace {
+
+constexpr int kCostOut = 62;
+constexpr int kBig = 0x3fff;        // L of lanes past the disparity range
+constexpr int kTileW = 64, kTileH = 16;
+
+// ------------------------------------------------------------------ census
+// blockIdx.z = 2 frame + side (0 left, 1 right).  The tile and its halo go
+// through LDS; pixels outside the image are stored as 256, which is never
+// darker than a centre.
+__global__ __launch_bounds__(256) void census_kernel(const uint8_t* __restrict__ left,
+                                                     const uint8_t* __restrict__ right, int W,
+                                                     int H, uint64_t* __restrict__ cl,
+                                                     uint64_t* __restrict__ cr) {
+    __shared__ uint16_t tile[kTileH + 6][kTileW + 8];
+    const int f = blockIdx.z >> 1, side = blockIdx.z & 1;
+    const size_t off = (size_t)f * (size_t)W * (size_t)H;
+    const uint8_t* img = (side ? right : left) + off;
+    uint64_t* out = (side ? cr : cl) + off;
+    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+    for (int i = threadIdx.x; i < (kTileH + 6) * (kTileW + 8); i += 256) {
+        const int ty = i / (kTileW + 8), tx = i - ty * (kTileW + 8);
+        const int y = y0 + ty - 3, x = x0 + tx - 4;
+        tile[ty][tx] = (y >= 0 && y < H && x >= 0 && x < W) ? img[(size_t)y * W + x] : 256;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 63;
+    const int x = x0 + tx;
+    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
+        const int y = y0 + r;
+        if (y >= H || x >= W) continue;
+        const int c = tile[r + 3][tx + 4];
+        uint32_t lo = 0u, hi = 0u;
+        int b = 0;
+#pragma unroll
+        for (int dy = 0; dy < 7; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 9; ++dx) {
+                if (dy == 3 && dx == 4) continue;
+                const uint32_t bit = tile[r + dy][tx + dx] < c ? 1u : 0u;
+                if (b < 32) lo |= bit << b;
+                else hi |= bit << (b - 32);
+                ++b;
+            }
+        }
+        out[(size_t)y * W + x] = ((uint64_t)hi << 32) | lo;
+    }
+}
+
+// ------------------------------------------------------------------ wave helpers
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_i(int old, int x) {
+    return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
+}
+
+// Minimum over the 64 lanes: row minima by DPP row shifts (lanes whose
+// source lies outside the row keep kBig), then the four row results.
+__device__ __forceinline__ int wave_min(int x) {
+    x = min(x, dpp_i<0x111, 0xf>(kBig, x));   // row_shr:1
+    x = min(x, dpp_i<0x112, 0xf>(kBig, x));   // row_shr:2
+    x = min(x, dpp_i<0x114, 0xf>(kBig, x));   // row_shr:4
+    x = min(x, dpp_i<0x118, 0xf>(kBig, x));   // row_shr:8
+    const int a = __builtin_amdgcn_readlane(x, 15), b = __builtin_amdgcn_readlane(x, 31);
+    const int c = __builtin_amdgcn_readlane(x, 47), d = __builtin_amdgcn_readlane(x, 63);
+    return min(min(a, b), min(c, d));
+}
+
+// Minimum of non-negative keys over the 64 lanes (selection keys stay
+// below 2^23; lanes without a key hold kNoKey).
+constexpr int kNoKey = 0x7fffffff;
+__device__ __forceinline__ int wave_min_key(int v) {
+    v = min(v, dpp_i<0x111, 0xf>(kNoKey, v));
+    v = min(v, dpp_i<0x112, 0xf>(kNoKey, v));
+    v = min(v, dpp_i<0x114, 0xf>(kNoKey, v));
+    v = min(v, dpp_i<0x118, 0xf>(kNoKey, v));
+    const int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
+    const int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
+    return min(min(a, b), min(c, d));
+}
+
+// lane l receives lane l-1's x (lane 0 receives kBig), and lane l+1's
+__device__ __forceinline__ int from_below(int x) { return dpp_i<0x138, 0xf>(kBig, x); }  // wave_shr:1
+__device__ __forceinline__ int from_above(int x) { return dpp_i<0x130, 0xf>(kBig, x); }  // wave_shl:1
+
+__device__ __forceinline__ int popc64(uint64_t v) {
+    return __builtin_popcount((uint32_t)v) + __builtin_popcount((uint32_t)(v >> 32));
+}
+
+// DPL consecutive uint16 of S at element offset e (e a multiple of DPL)
+template <int DPL>
+__device__ __forceinline__ void load_s(const uint16_t* S, size_t e, int (&v)[DPL]) {
+    if constexpr (DPL == 1) {
+        v[0] = S[e];
+    } else if constexpr (DPL == 2) {
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(S + e);
+        v[0] = (int)(w & 0xffffu);
+        v[1] = (int)(w >> 16);
+    } else {
+        const uint2 w = *reinterpret_cast<const uint2*>(S + e);
+        v[0] = (int)(w.x & 0xffffu);
+        v[1] = (int)(w.x >> 16);
+        v[2] = (int)(w.y & 0xffffu);
+        v[3] = (int)(w.y >> 16);
+    }
+}
+template <int DPL>
+__device__ __forceinline__ void store_s(uint16_t* S, size_t e, const int (&v)[DPL]) {
+    if constexpr (DPL == 1) {
+        S[e] = (uint16_t)v[0];
+    } else if constexpr (DPL == 2) {
+        *reinterpret_cast<uint32_t*>(S + e) = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    } else {
+        *reinterpret_cast<uint2*>(S + e) =
+            make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+    }
+}
+
+enum { kFirst = 0, kAdd = 1, kFinal = 2 };
+
+// One path line per wave (a workgroup of one wave).  DIR: 0 left to right,
+// 1 right to left, 2 top to bottom, 3 bottom to top.  MODE: kFirst writes S,
+// kAdd adds to it, kFinal (left to right only) selects and checks.
+template <int DPL, int DIR, int MODE>
+__global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
+    static_assert(MODE != kFinal || DIR == 0, "the final pass runs left to right");
+    extern __shared__ uint32_t lds[];                  // kFinal: keyR[W], then dL[W] (int16)
+    constexpr bool HORZ = DIR <= 1;
+    const int lane = threadIdx.x;
+    const int W = a.W, H = a.H, D = a.D;
+    const int lines = HORZ ? H : W;
+    const int f = blockIdx.x / lines, line = blockIdx.x - f * lines;
+    const size_t fo = (size_t)f * (size_t)W * (size_t)H;
+    const uint64_t* __restrict__ cl = a.cl + fo;
+    const uint64_t* __restrict__ cr = a.cr + fo;
+    uint16_t* __restrict__ S = a.S + fo * (size_t)D;
+    const int steps = HORZ ? W : H;
+    const int d0 = lane * DPL;
+    const int P1 = a.P1, P2 = a.P2;
+
+    uint32_t* keyR = lds;
+    int16_t* dLrow = reinterpret_cast<int16_t*>(lds + (MODE == kFinal ? W : 0));
+    if constexpr (MODE == kFinal) {
+        for (int x = lane; x < W; x += 64) keyR[x] = 0xffffffffu;
+        __syncthreads();
+    }
+
+    // pixel of step s
+    auto pixel = [&](int s, int& y, int& x) {
+        if constexpr (DIR == 0) { y = line; x = s; }
+        else if constexpr (DIR == 1) { y = line; x = W - 1 - s; }
+        else if constexpr (DIR == 2) { y = s; x = line; }
+        else { y = H - 1 - s; x = line; }
+    };
+    // the census operands of step s (loaded a step ahead)
+    auto load_ops = [&](int s, uint64_t& clv, uint64_t (&crv)[DPL]) {
+        int y, x;
+        pixel(s, y, x);
+        clv = cl[(size_t)y * W + x];
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) {
+            const int xr = x - (d0 + i);
+            crv[i] = xr >= 0 ? cr[(size_t)y * W + xr] : 0ull;
+        }
+    };
+
+    int Lp[DPL];
+    int M = 0;
+    uint64_t clv, crv[DPL];
+    load_ops(0, clv, crv);
+    for (int s = 0; s < steps; ++s) {
+        int y, x;
+        pixel(s, y, x);
+        const uint64_t clc = clv;
+        uint64_t crc[DPL];
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) crc[i] = crv[i];
+        if (s + 1 < steps) load_ops(s + 1, clv, crv);
+
+        int L[DPL];
+        if (s == 0) {
+#pragma unroll
+            for (int i = 0; i < DPL; ++i) {
+                const int d = d0 + i;
+                const int c = (x - d >= 0) ? popc64(clc ^ crc[i]) : kCostOut;
+                L[i] = d < D ? c : kBig;
+            }
+        } else {
+            const int below = from_below(Lp[DPL - 1]);   // L(d0 - 1)
+            const int above = from_above(Lp[0]);         // L(d0 + DPL)
+            const int jump = M + P2;
+#pragma unroll
+            for (int i = 0; i < DPL; ++i) {
+                const int d = d0 + i;
+                const int lo = i > 0 ? Lp[i - 1] : below;
+                const int hi = i + 1 < DPL ? Lp[i + 1] : above;
+                const int t = min(min(Lp[i], min(lo, hi) + P1), jump);
+                const int c = (x - d >= 0) ? popc64(clc ^ crc[i]) : kCostOut;
+                L[i] = d < D ? c + t - M : kBig;
+            }
+        }
+        int m = L[0];
+#pragma unroll
+        for (int i = 1; i < DPL; ++i) m = min(m, L[i]);
+        M = wave_min(m);
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) Lp[i] = L[i];
+
+        const size_t e = ((size_t)y * W + x) * (size_t)D + (size_t)d0;
+        const bool live = d0 < D;
+        if constexpr (MODE == kFirst) {
+            if (live) store_s<DPL>(S, e, L);
+        } else if constexpr (MODE == kAdd) {
+            if (live) {
+                int v[DPL];
+                load_s<DPL>(S, e, v);
+#pragma unroll
+                for (int i = 0; i < DPL; ++i) v[i] += L[i];
+                store_s<DPL>(S, e, v);
+            }
+        } else {
+            // final summed costs of pixel (y, x): select d_L and offer every
+            // d to the right view's column x - d
+            int key = kNoKey;
+            if (live) {
+                int v[DPL];
+                load_s<DPL>(S, e, v);
+#pragma unroll
+                for (int i = 0; i < DPL; ++i) {
+                    const int d = d0 + i;
+                    const int k = ((v[i] + L[i]) << 8) | d;
+                    key = min(key, k);
+                    if (x - d >= 0) atomicMin(&keyR[x - d], (uint32_t)k);
+                }
+            }
+            const int kmin = wave_min_key(key);
+            if (lane == 0) dLrow[x] = (int16_t)(kmin & 0xff);
+        }
+    }
+    if constexpr (MODE == kFinal) {
+        __syncthreads();
+        float* out = a.disp + fo + (size_t)line * W;
+        for (int x = lane; x < W; x += 64) {
+            const int d = dLrow[x];
+            float v = -1.0f;
+            if (x - d >= 0) {
+                const int e = (int)(keyR[x - d] & 0xffu);
+                if (abs(d - e) <= 1) v = (float)d;
+            }
+            out[x] = v;
+        }
+    }
+}
+
+template <int DPL>
+hipError_t launch_paths(const PathArgs& a, int frames, hipStream_t st) {
+    const unsigned rows = (unsigned)(frames * a.H), cols = (unsigned)(frames * a.W);
+    hipLaunchKernelGGL((path_kernel<DPL, 2, kFirst>), dim3(cols), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((path_kernel<DPL, 3, kAdd>), dim3(cols), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((path_kernel<DPL, 1, kAdd>), dim3(rows), dim3(64), 0, st, a);
+    const size_t lds = (size_t)a.W * sizeof(uint32_t) + (size_t)a.W * sizeof(int16_t);
+    hipLaunchKernelGGL((path_kernel<DPL, 0, kFinal>), dim3(rows), dim3(64), lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int dpl_of(int D) { return D <= 64 ? 1 : (D <= 128 ? 2 : 4); }
+
+hipError_t launch_sgm(const uint8_t* left, const uint8_t* right, int W, int H, int frames,
+                      const SgmWorkspace& ws, int D, int P1, int P2, float* disp, hipStream_t st) {
+    dim3 grid((unsigned)((W + kTileW - 1) / kTileW), (unsigned)((H + kTileH - 1) / kTileH),
+              (unsigned)(2 * frames));
+    hipLaunchKernelGGL(census_kernel, grid, dim3(256), 0, st, left, right, W, H, ws.cl, ws.cr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    PathArgs a{ws.cl, ws.cr, ws.S, disp, W, H, D, P1, P2};
+    switch (dpl_of(D)) {
+        case 1: return launch_paths<1>(a, frames, st);
+        case 2: return launch_paths<2>(a, frames, st);
+        default: return launch_paths<4>(a, frames, st);
+    }
+}
+
+}  // namespace stx::sgm
+
+// ------------------------------------------------------------------ C ABI
+struct stixels_sgm {
+    stixels_sgm_params p{};
+    stx::sgm::SgmWorkspace ws{};
+    size_t bytes = 0;
+    int last_W = 0, last_H = 0, device = 0;
+    std::string err;
+};
+
+namespace {
+
+int sgm_fail(stixels_sgm* m, int code, const std::string& msg) {
+    if (m) m->err = msg;
+    return code;
+}
+
+thread_local std::string g_sgm_create_error;
+
+}  // namespace
+
+extern "C" {
+
+int stixels_sgm_create(const stixels_sgm_params* params, stixels_sgm** out) {
+    if (!params || !out) return STIXELS_E_INVALID_ARG;
+    *out = nullptr;
+    const stixels_sgm_params& p = *params;
+    const char* why = nullptr;
+    if (p.max_width < 1 || p.max_height < 1) why = "max_width and max_height must be >= 1";
+    else if (p.max_disparity < 4 || p.max_disparity > 256 || p.max_disparity % 4 != 0)
+        why = "max_disparity must be a multiple of 4 in 4..256";
+    else if (p.p1 < 0 || p.p2 < p.p1 || p.p2 > 1000) why = "penalties need 0 <= p1 <= p2 <= 1000";
+    else if (p.paths != 4) why = "paths must be 4 (the four axis directions)";
+    else if (p.max_frames < 1) why = "max_frames must be >= 1";
+    else if (p.max_width > 8192) why = "max_width must be <= 8192 (a row's selection state in LDS)";
+    if (why) {
+        g_sgm_create_error = why;
+        return STIXELS_E_INVALID_ARG;
+    }
+    stixels_sgm* m = new (std::nothrow) stixels_sgm;
+    if (!m) return STIXELS_E_NOMEM;
+    m->p = p;
+    (void)hipGetDevice(&m->device);
+    const size_t n = (size_t)p.max_frames * (size_t)p.max_width * (size_t)p.max_height;
+    const size_t nd = n * (size_t)p.max_disparity;
+    bool ok = hipMalloc(reinterpret_cast<void**>(&m->ws.cl), n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void**>(&m->ws.cr), n * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void**>(&m->ws.S), nd * sizeof(uint16_t)) == hipSuccess;
+    m->bytes = 2 * n * sizeof(uint64_t) + nd * sizeof(uint16_t);
+    if (!ok) {
+        (void)hipFree(m->ws.cl);
+        (void)hipFree(m->ws.cr);
+        (void)hipFree(m->ws.S);
+        delete m;
+        g_sgm_create_error = "hipMalloc of the matching workspace failed";
+        return STIXELS_E_NOMEM;
+    }
+    *out = m;
+    return STIXELS_OK;
+}
+
+int stixels_sgm_destroy(stixels_sgm* m) {
+    if (!m) return STIXELS_OK;
+    (void)hipFree(m->ws.cl);
+    (void)hipFree(m->ws.cr);
+    (void)hipFree(m->ws.S);
+    delete m;
+    return STIXELS_OK;
+}
+
+const char* stixels_sgm_last_error(const stixels_sgm* m) {
+    return m ? m->err.c_str() : g_sgm_create_error.c_str();
+}
+
+int stixels_sgm_device_bytes(const stixels_sgm* m, size_t* bytes) {
+    if (!m || !bytes) return STIXELS_E_INVALID_ARG;
+    *bytes = m->bytes;
+    return STIXELS_OK;
+}
+
+int stixels_sgm_compute(stixels_sgm* m, const uint8_t* d_left, const uint8_t* d_right,
+                        int32_t width, int32_t height, int32_t frames, void* stream,
+                        float* d_disparity) {
+    if (!m) return STIXELS_E_INVALID_ARG;
+    if (!d_left || !d_right || !d_disparity)
+        return sgm_fail(m, STIXELS_E_INVALID_ARG, "null image or disparity pointer");
+    if (width < 1 || width > m->p.max_width || height < 1 || height > m->p.max_height)
+        return sgm_fail(m, STIXELS_E_INVALID_ARG, "width or height outside the handle's maximum");
+    if (frames < 1 || frames > m->p.max_frames)
+        return sgm_fail(m, STIXELS_E_INVALID_ARG, "frames outside [1, max_frames]");
+    const hipError_t e =
+        stx::sgm::launch_sgm(d_left, d_right, width, height, frames, m->ws, m->p.max_disparity,
+                             m->p.p1, m->p.p2, d_disparity, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return sgm_fail(m, STIXELS_E_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    m->last_W = width;
+    m->last_H = height;
+    return STIXELS_OK;
+}
+
+int stixels_sgm_debug(const stixels_sgm* m, int32_t which, void* host_dst, size_t bytes) {
+    if (!m || !host_dst || which < 0 || which > 2) return STIXELS_E_INVALID_ARG;
+    const size_t n = (size_t)m->last_W * (size_t)m->last_H;
+    if (n == 0) return STIXELS_E_INVALID_ARG;
+    const void* src = which == 0 ? (const void*)m->ws.cl
+                                 : (which == 1 ? (const void*)m->ws.cr : (const void*)m->ws.S);
+    const size_t need = which == 2 ? n * (size_t)m->p.max_disparity * sizeof(uint16_t)
+                                   : n * sizeof(uint64_t);
+    if (bytes < need) return STIXELS_E_INVALID_ARG;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost) != hipSuccess)
+        return STIXELS_E_HIP;
+    return STIXELS_OK;
+}
+
+int stixels_compute_stereo(stixels_handle* h, stixels_sgm* m, const uint8_t* d_left,
+                           const uint8_t* d_right, int32_t width, int32_t height, void* stream,
+                           float* d_disparity, const stixels_output* out) {
+    if (!h || !m) return STIXELS_E_INVALID_ARG;
+    if (m->p.max_disparity != h->p.max_disparity || h->p.subpixel_log2 != 0) {
+        h->err = "the matching handle's max_disparity must equal the stixel handle's (whole pixels)";
+        return STIXELS_E_INVALID_ARG;
+    }
+    int rc = stixels_sgm_compute(m, d_left, d_right, width, height, 1, stream, d_disparity);
+    if (rc != STIXELS_OK) {
+        h->err = m->err;
+        return rc;
+    }
+    return stixels_compute(h, d_disparity, width, height, stream, out);
+}
+
+}  // extern "C"
