@@ -21,6 +21,7 @@ sky minima are separable) is reported beside it.
 
     python bench.py [--steps K] [--warmup W]          the JSON line
     python bench.py --profile-mode MODE [--launches N] one workload for rocprofv3
+    python bench.py --profile-mode batch --phase-timing the per-phase split of a task
 """
 
 from __future__ import annotations
@@ -545,8 +546,13 @@ def profile_mode(args):
         b = P.Batch(len(frames), len(frames) * (Wp // 5), Hp, D, args.workgroups)
         b.set_waves(args.waves)
         b.capture(list(zip([h] * len(frames), frames, outs)), stream)
+        if args.phase_timing:
+            b.replay(stream)                         # warm, then count the timed launches only
+            b.phase_cycles(reset=True)
         for _ in range(args.launches):
             b.replay(stream)
+        if args.phase_timing:
+            print(json.dumps(phase_split(b, args.launches)), flush=True)
     else:
         h.set_frame_path(1 if args.profile_mode == "frame" else 2)
         for _ in range(args.launches):
@@ -554,6 +560,20 @@ def profile_mode(args):
                 h.compute(f, o, stream)
     torch.cuda.synchronize()
     print(f"{args.profile_mode}: {args.launches} launches over {len(frames)} frames", flush=True)
+
+
+def phase_split(batch, launches):
+    """Per-task shader cycles of each phase of the persistent kernel and its
+    share of the tasks' summed time (a library built with phase timing)."""
+    c = batch.phase_cycles()
+    g, _ = batch.info()
+    tasks = max(1, c["tasks"])
+    names = ("reduce", "prefix_scans", "object_table", "recurrence", "backtracking")
+    total = sum(c[n] for n in names)
+    return {"workgroups": g, "launches": launches, "tasks": c["tasks"],
+            "cycles_per_task": {n: round(c[n] / tasks, 1) for n in names},
+            "share": {n: round(c[n] / max(1, total), 4) for n in names},
+            "task_cycles_over_lifetime": round(total / max(1, c["workgroup_lifetime"]), 4)}
 
 
 # ------------------------------------------------------------------ main
@@ -576,7 +596,13 @@ def main():
                     help="profile modes: resident workgroups of the batched launch (0: occupancy)")
     ap.add_argument("--placement", type=int, default=0,
                     help="profile modes: object prefix table placement (0 auto, 1 HBM, 2 LDS)")
+    ap.add_argument("--phase-timing", action="store_true",
+                    help="profile modes batch/hires: load the library built with phase timing "
+                         "(python -m paper_1610_04124_amd.build --phase-timing) and print the "
+                         "per-phase split of the column tasks")
     args = ap.parse_args()
+    if args.phase_timing:
+        os.environ["STIXELS_PHASE_TIMING"] = "1"        # before the binding loads a library
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(frames and columns are independent, see the design notes "

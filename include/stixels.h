@@ -369,6 +369,18 @@ int stixels_batch_device_bytes(const stixels_batch *b, size_t *bytes);
 int stixels_batch_info(const stixels_batch *b, int32_t *workgroups, int32_t *tasks);
 const char *stixels_batch_last_error(const stixels_batch *b);
 
+/* Profiling only.  Shader-clock cycles that wave 0 of the persistent
+ * kernel's workgroups spent in each phase of the column tasks of this
+ * batch's launches (Sec. 4.1 reduction, the four small prefix scans and the
+ * object prefix table of Sec. 4.2, the recurrence of Sec. 4.3, the
+ * backtracking of Sec. 4.4), then the number of tasks and the workgroups'
+ * summed lifetimes: 7 values into host_dst[0..n) (zeros past 7).
+ * Synchronises the device; reset != 0 clears the sums.  Only a library
+ * built with STX_PHASE_TIMING counts (python -m paper_1610_04124_amd.build
+ * --phase-timing, which writes libstixels_phases.so); the regular library
+ * returns STIXELS_E_INVALID_ARG. */
+int stixels_batch_phase_cycles(stixels_batch *b, uint64_t *host_dst, int32_t n, int32_t reset);
+
 /* ------------------------------------------------------------------ debug
  * Host copies of the handle's offline tables (Sec. 3.4), for parity tests.
  * Here and below d_range counts disparity bins (max_disparity <<

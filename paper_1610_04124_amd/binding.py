@@ -16,6 +16,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstixels.so")
+#: the same library built with per-phase clock stamps in the persistent
+#: kernel (profiling only); STIXELS_PHASE_TIMING=1 in the environment loads it
+PHASES_LIB_PATH = os.path.join(_HERE, "libstixels_phases.so")
 
 OK, E_INVALID_ARG, E_RANGE, E_HIP, E_NOMEM = 0, -1, -2, -3, -4
 FLAG_BATCH_ONLY = 1
@@ -39,7 +42,7 @@ EXPORTS = (
     "stixels_set_object_lut", "stixels_compute_noalloc",
     "stixels_sgm_create", "stixels_sgm_destroy", "stixels_sgm_last_error",
     "stixels_sgm_device_bytes", "stixels_sgm_compute", "stixels_sgm_debug",
-    "stixels_compute_stereo",
+    "stixels_compute_stereo", "stixels_batch_phase_cycles",
 )
 
 
@@ -120,15 +123,16 @@ def lib():
     """Load the in-tree HIP library; raise if it has not been built."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with "
+        path = PHASES_LIB_PATH if os.environ.get("STIXELS_PHASE_TIMING") == "1" else LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
                               "`python -m paper_1610_04124_amd.build` (no CPU fallback exists)")
         # torch ships its own HIP runtime (SONAME libamdhip64.so.7) and loads
         # it under another file name; importing torch first lets this
         # library's libamdhip64.so.7 dependency bind to that same runtime, so
         # the process holds one HIP runtime and shares devices and streams.
         import torch  # noqa: F401
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         vp, i32, P = C.c_void_p, C.c_int32, C.POINTER
         L.stixels_create.argtypes = [P(Params), P(vp)]
         L.stixels_destroy.argtypes = [vp]
@@ -170,6 +174,7 @@ def lib():
         L.stixels_batch_device_bytes.argtypes = [vp, P(C.c_size_t)]
         L.stixels_debug_stage_times.argtypes = [vp, vp, i32, i32, vp, P(Output),
                                                 P(C.c_float)]
+        L.stixels_batch_phase_cycles.argtypes = [vp, P(C.c_uint64), i32, i32]
         L.stixels_batch_last_error.argtypes = [vp]
         L.stixels_batch_last_error.restype = C.c_char_p
         L.stixels_sgm_create.argtypes = [P(SgmParams), P(vp)]
@@ -681,6 +686,19 @@ class Batch:
         if rc != OK:
             self._err(rc, "stixels_batch_info")
         return g.value, t.value
+
+    #: names of the values phase_cycles returns
+    PHASES = ("reduce", "prefix_scans", "object_table", "recurrence", "backtracking",
+              "tasks", "workgroup_lifetime")
+
+    def phase_cycles(self, reset: bool = False) -> dict:
+        """Shader-clock cycles per task phase summed over this batch's
+        launches (the library built with phase timing only)."""
+        buf = (C.c_uint64 * 7)()
+        rc = lib().stixels_batch_phase_cycles(self.b, buf, 7, 1 if reset else 0)
+        if rc != OK:
+            self._err(rc, "stixels_batch_phase_cycles")
+        return dict(zip(self.PHASES, (int(x) for x in buf)))
 
 
 class Sgm:

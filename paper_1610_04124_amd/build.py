@@ -1,6 +1,9 @@
 """Build step of the HIP library: hipcc for gfx950 into an in-tree shared object.
 
-    python -m paper_1610_04124_amd.build
+    python -m paper_1610_04124_amd.build                  libstixels.so
+    python -m paper_1610_04124_amd.build --phase-timing   libstixels_phases.so: the
+        same kernels with shader-clock stamps at each phase of a column task in
+        the persistent kernel (profiling only; loaded when STIXELS_PHASE_TIMING=1)
 """
 
 from __future__ import annotations
@@ -15,6 +18,7 @@ from concurrent.futures import ThreadPoolExecutor
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB = os.path.join(_HERE, "libstixels.so")
+PHASES_LIB = os.path.join(_HERE, "libstixels_phases.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,9 +41,12 @@ def sources():
     return sorted(glob.glob(os.path.join(_HERE, "csrc", "*.hip")), key=key)
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, phase_timing: bool = False) -> str:
     """Compiles every source to an object in parallel, then links the library."""
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(_HERE, "csrc")]
+    if phase_timing:
+        inc.append("-DSTX_PHASE_TIMING=1")
+    lib_path = PHASES_LIB if phase_timing else LIB
     with tempfile.TemporaryDirectory(prefix="stixels_build_") as tmpdir:
         objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in sources()]
         cmds = [[HIPCC, *FLAGS, *inc, "-c", src, "-o", obj]
@@ -52,11 +59,11 @@ def build(verbose: bool = False) -> str:
 
         with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
             list(ex.map(run, cmds))
-        tmp = LIB + ".tmp"
+        tmp = lib_path + ".tmp"
         run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, phase_timing="--phase-timing" in sys.argv))

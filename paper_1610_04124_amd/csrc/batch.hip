@@ -78,6 +78,7 @@ struct stixels_batch {
     int last_columns = 0;
     int last_grid = 0, last_tasks = 0, last_waves = 0;
     bool links = false;     // the staged jobs need the recurrence with stored links
+    unsigned long long* d_phase = nullptr;   // phase cycles (STX_PHASE_TIMING builds)
     std::string err;
 };
 
@@ -147,6 +148,7 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     for (int i = 0; i < n; ++i) {
         const stixels_job& j = jobs[i];
         b->h_jobs[i] = make_job_desc(j.handle, j.d_disparity, j.width, j.height, j.out);
+        b->h_jobs[i].phase = b->d_phase;
         b->links = b->links || !j.handle->prior.exact;
         if (!j.use_pose) continue;
         if (!b->d_pose_area)
@@ -288,6 +290,13 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
             hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
         if (!ok) rc = STIXELS_E_NOMEM;
     }
+#ifdef STX_PHASE_TIMING
+    if (rc == STIXELS_OK &&
+        (hipMalloc(reinterpret_cast<void**>(&b->d_phase), sizeof(unsigned long long) * kPhaseSlots) !=
+             hipSuccess ||
+         hipMemset(b->d_phase, 0, sizeof(unsigned long long) * kPhaseSlots) != hipSuccess))
+        rc = STIXELS_E_NOMEM;
+#endif
     if (rc == STIXELS_OK && (cfg->flags & STIXELS_BATCH_POSES)) {
         b->pose_area_bytes = (size_t)cfg->max_height *
                              ((size_t)cfg->max_disparity * sizeof(float) + 2 * sizeof(int32_t));
@@ -318,6 +327,7 @@ int stixels_batch_destroy(stixels_batch* b) {
     (void)hipFree(b->d_jobs_g);
     (void)hipFree(b->d_tasks_g);
     (void)hipFree(b->d_counter_g);
+    (void)hipFree(b->d_phase);
     (void)hipFree(b->d_scratch);
     (void)hipFree(b->d_pose_area);
     (void)hipFree(b->d_pose_items);
@@ -501,6 +511,23 @@ int stixels_compute_batch(const stixels_job* jobs, int32_t n, void* stream) {
     const int rc = stixels_batch_compute(b, jobs, n, stream);
     if (rc != STIXELS_OK) owner->err = b->err;
     return rc;
+}
+
+int stixels_batch_phase_cycles(stixels_batch* b, uint64_t* host_dst, int32_t n, int32_t reset) {
+    if (!b || !host_dst || n < 1) return STIXELS_E_INVALID_ARG;
+#ifdef STX_PHASE_TIMING
+    unsigned long long h[kPhaseSlots] = {};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(h, b->d_phase, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess ||
+        (reset && hipMemset(b->d_phase, 0, sizeof(h)) != hipSuccess))
+        return bfail(b, STIXELS_E_HIP, "reading the phase cycles failed");
+    for (int i = 0; i < n; ++i) host_dst[i] = (i < kPhaseSlots) ? (uint64_t)h[i] : 0u;
+    return STIXELS_OK;
+#else
+    (void)reset;
+    return bfail(b, STIXELS_E_INVALID_ARG,
+                 "this library was built without phase timing (STX_PHASE_TIMING)");
+#endif
 }
 
 const char* stixels_batch_last_error(const stixels_batch* b) {

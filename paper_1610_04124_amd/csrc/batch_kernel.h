@@ -40,6 +40,18 @@ struct JobDesc {
     int W, H, s, ncols, D, vtop, reduce_mode, cap;
     int sub;              // disparity bins of 2^-sub px
     Prior prior;
+    // shader-clock cycles per task phase, summed over the launch (builds
+    // with STX_PHASE_TIMING only; null and unused otherwise)
+    unsigned long long* phase;
+};
+
+// Phases of a column task timed by STX_PHASE_TIMING builds: reduction (with
+// the column's disparity range), the four small prefix scans, the object
+// prefix table, the recurrence, the backtracking; then the task count and
+// the workgroups' summed lifetime (start delay and final waits included).
+enum PhaseSlot {
+    kPhaseReduce = 0, kPhaseScans, kPhaseObjectTable, kPhaseRecurrence, kPhaseBacktrack,
+    kPhaseTasks, kPhaseLifetime, kPhaseSlots = 8
 };
 
 __device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D, int sub) {
@@ -93,6 +105,15 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
     (void)hmax;
+#ifdef STX_PHASE_TIMING
+    // wave 0 stamps the shader clock at each phase boundary of a task
+    const unsigned long long t_entry = __builtin_amdgcn_s_memtime();
+    unsigned long long* phase_acc = nullptr;
+    __shared__ unsigned long long t_rec_end;
+    auto phase_add = [&](int slot, unsigned long long v) {
+        if (threadIdx.x == 0 && phase_acc) atomicAdd(phase_acc + slot, v);
+    };
+#endif
     // Workgroups are dispatched to the eight XCDs in turn.  When every
     // column takes equally long, all of them would reach the memory-heavy
     // table builds together, round after round; starting XCD x stagger * x
@@ -118,6 +139,10 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         const int2 tk = tasks[t];
         const JobDesc& J = jobs[tk.x];
         const int H = J.H, D = J.D, col = tk.y, stride = H + 1;
+#ifdef STX_PHASE_TIMING
+        phase_acc = J.phase;
+        const unsigned long long t0 = __builtin_amdgcn_s_memtime();
+#endif
 
         // Sec. 4.1: reduce this column's strips, bottom-up, into LDS
         int lmin = INT_MAX, lmax = -1;
@@ -164,6 +189,10 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         fmin = __builtin_amdgcn_readfirstlane(fmin);
         fmax = __builtin_amdgcn_readfirstlane(fmax);
         __syncthreads();
+#ifdef STX_PHASE_TIMING
+        const unsigned long long t1 = __builtin_amdgcn_s_memtime();
+        unsigned long long t2 = t1;
+#endif
 
         // Sec. 4.2: prefix tables into the scratch slot: the four small ones
         // by wave 0, the object rows f = fmin + wave, fmin + wave + W, ...
@@ -212,6 +241,10 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
                 ca = readlane_f(aa, 63);
                 cn = readlane_f(nn, 63);
             }
+#ifdef STX_PHASE_TIMING
+            __builtin_amdgcn_s_waitcnt(0);
+            t2 = __builtin_amdgcn_s_memtime();
+#endif
         }
         const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
         // the column's object rows, stored through one buffer resource with a
@@ -266,6 +299,9 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             }
         }
         __syncthreads();   // the tables written above are read back below, by every wave
+#ifdef STX_PHASE_TIMING
+        const unsigned long long t3 = __builtin_amdgcn_s_memtime();
+#endif
 
         // Sec. 4.3-4.4
         ColumnIn in;
@@ -289,9 +325,27 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         out.total = J.total + col;
         out.overflow = J.overflow + col;
         out.cap = J.cap;
+#ifdef STX_PHASE_TIMING
+        out.t_rec_end = &t_rec_end;
+#endif
         solve_column<S, NCH, W, false, true, LINKS>(H, J.vtop, J.prior, in, out, lds);
+#ifdef STX_PHASE_TIMING
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_s_waitcnt(0);
+            const unsigned long long t5 = __builtin_amdgcn_s_memtime();
+            phase_add(kPhaseReduce, t1 - t0);
+            phase_add(kPhaseScans, t2 - t1);
+            phase_add(kPhaseObjectTable, t3 - t2);
+            phase_add(kPhaseRecurrence, t_rec_end - t3);
+            phase_add(kPhaseBacktrack, t5 - t_rec_end);
+            phase_add(kPhaseTasks, 1ull);
+        }
+#endif
         __syncthreads();   // every read of the slot completes before the next task rewrites it
     }
+#ifdef STX_PHASE_TIMING
+    phase_add(kPhaseLifetime, __builtin_amdgcn_s_memtime() - t_entry);
+#endif
 }
 
 // Sec. 4.1-4.2 for one column by one wave: its strips reduced into qs (LDS,

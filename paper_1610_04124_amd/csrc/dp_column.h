@@ -85,6 +85,9 @@ struct ColumnOut {
     float* total;
     uint8_t* overflow;
     int cap;
+#ifdef STX_PHASE_TIMING
+    unsigned long long* t_rec_end = nullptr;   // shader clock when the recurrence ends
+#endif
 };
 
 // Emitted stixel, kept by lane t (t-th stixel found from the top).
@@ -886,6 +889,9 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     }
     __syncthreads();
     if (wave != 0) return;
+#ifdef STX_PHASE_TIMING
+    if (lane == 0 && out.t_rec_end) *out.t_rec_end = __builtin_amdgcn_s_memtime();
+#endif
 
     if constexpr (LINKS) {
         backtrack_links<S>(H, vtop, P, in, out, L);

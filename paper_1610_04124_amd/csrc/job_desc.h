@@ -33,6 +33,7 @@ inline JobDesc make_job_desc(const stixels_handle* h, const float* disp, int W, 
     d.sub = h->p.subpixel_log2;
     d.cap = out.capacity;
     d.prior = h->prior;
+    d.phase = nullptr;
     return d;
 }
 

@@ -36,6 +36,24 @@ def test_library_exports_every_declared_symbol():
     assert sorted(B.EXPORTS) == names
 
 
+def test_phase_timing_library_exports_the_same_symbols():
+    """The profiling build (kernels with phase stamps) is the same library:
+    every declared entry point, loaded in a process of its own."""
+    if not os.path.exists(B.PHASES_LIB_PATH):
+        pytest.skip("libstixels_phases.so not built")
+    code = ("import ctypes, sys; L = ctypes.CDLL(sys.argv[1]); "
+            "print(' '.join(n for n in sys.argv[2:] if not hasattr(L, n)))")
+    # torch first, as the binding does, so that the HIP runtime resolves
+    out = subprocess.run(["python", "-c", "import torch; " + code, B.PHASES_LIB_PATH,
+                          *declared_functions()], check=True, capture_output=True, text=True)
+    assert out.stdout.strip() == ""
+
+
+def test_phase_cycles_reject_bad_arguments():
+    buf = (ctypes.c_uint64 * 7)()
+    assert P.lib().stixels_batch_phase_cycles(None, buf, 7, 0) == B.E_INVALID_ARG
+
+
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
