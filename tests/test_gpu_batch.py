@@ -140,6 +140,41 @@ def test_uneven_batch_matches_oracle(workgroups, waves):
         assert_frames_equal(out.to_host(), oracle.frame(p, disp), f"uneven frame {i}")
 
 
+def test_uneven256_every_frame_in_one_launch():
+    """The whole uneven workload (256 frames, four sizes, stixel widths 3/5/7,
+    own camera and disparity range per size) in one persistent launch: every
+    frame bitwise equal to the same frame through the per-frame path, and one
+    frame of every (size, stixel width) pair equal to the oracle."""
+    import torch
+    announce("uneven256: 256 frames in one launch vs per frame; oracle per size x width")
+    handles, items, infos = {}, [], []
+    for i in range(256):
+        disp, info = synth.workload_frame("uneven256", i)
+        W, H, s = info["width"], info["height"], info["stixel_width"]
+        key = (W, H, s, info["d_max"])
+        if key not in handles:
+            p = synth.make_params(camera=info["camera"], stixel_width=s,
+                                  max_disparity=info["d_max"], max_width=W, max_height=H)
+            handles[key] = (P.Stixels(p), p)
+        h, p = handles[key]
+        items.append((h, to_device(disp), h.new_output(W, H)))
+        infos.append((key, p, disp))
+    b = run_batch(items, 0, max_h=880, max_d=256)
+    assert b.info()[1] == sum(h.num_columns(d.shape[1]) for h, d, _ in items)
+    checked = set()
+    for i, ((h, d, out), (key, p, disp)) in enumerate(zip(items, infos)):
+        alone = h.new_output(key[0], key[1])
+        h.compute(d, alone)
+        torch.cuda.synchronize()
+        got = out.to_host()
+        assert_frames_equal(got, alone.to_host(), f"uneven256 frame {i} vs per frame")
+        if key[:3] not in checked:
+            checked.add(key[:3])
+            assert_frames_equal(got, oracle.frame(p, disp), f"uneven256 frame {i} vs oracle")
+    sizes = {(k[0], k[1]) for k in checked}
+    assert len(sizes) == 4 and len({k[2] for k in checked}) == 3, checked
+
+
 def test_graph_replays_are_stable_and_follow_inputs():
     """Capture once, replay several times with eager work and syncs between
     the replays; each replay equals the per-frame result of the inputs it
