@@ -185,7 +185,7 @@ int stage(stixels_batch* b, const stixels_job* jobs, int32_t n, int* slots, int*
     *slots = kernel_slots(hmax);
     *nch = kernel_chunks(dmax);
     *ntasks = t;
-    *stride = pairs ? 2LL * (8 + dmax) * (hmax + 1) : (long long)(4 + dmax) * (hmax + 1);
+    *stride = pairs ? 2LL * (8 + dmax) * (hmax + 1) : slot_floats(hmax, dmax);
     *pairs_out = pairs;
     *hmax_out = hmax;
     return STIXELS_OK;
@@ -266,8 +266,8 @@ int stixels_batch_create(const stixels_batch_config* cfg, stixels_batch** out) {
     if (rc == STIXELS_OK) rc = occupancy_grid(b, slots, kernel_chunks(cfg->max_disparity), 1, &grid);
     if (rc == STIXELS_OK && cfg->workgroups > 0) grid = std::min(grid, (int)cfg->workgroups);
     if (rc == STIXELS_OK) {
-        b->scratch_floats = (size_t)grid * (size_t)(4 + cfg->max_disparity) *
-                            (size_t)(cfg->max_height + 1);
+        b->scratch_floats = (size_t)grid *
+                            (size_t)slot_floats(cfg->max_height, cfg->max_disparity);
         // the two-column kernel, where it exists, needs two (8 + D)(h+1)
         // column slots per resident workgroup
         int pgrid = 0;

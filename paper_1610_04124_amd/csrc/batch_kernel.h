@@ -54,6 +54,18 @@ enum PhaseSlot {
     kPhaseTasks, kPhaseLifetime, kPhaseSlots = 8
 };
 
+// Scratch slot of one column task (floats): the ground, sky, disparity-sum
+// and count prefixes (H+1 each), then the object prefix rows.  Entry i of an
+// object row sits at float i + 3 of a 16-byte aligned row of
+// slot_row_floats(H) floats, so that entries 4l+1 .. 4l+4 (the prefixes a
+// lane holding rows 4l .. 4l+3 produces) form one aligned 16-byte store; the
+// row leaves room for a lane whose rows run past H.
+__host__ __device__ constexpr long long slot_row_floats(int H) { return ((H + 10) / 4) * 4; }
+__host__ __device__ constexpr long long slot_rows_offset(int H) { return ((4LL * (H + 1) + 3) / 4) * 4; }
+__host__ __device__ constexpr long long slot_floats(int H, int D) {
+    return slot_rows_offset(H) + (long long)D * slot_row_floats(H);
+}
+
 __device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D, int sub) {
     switch (s) {
 #define STX_CASE(n) case n: return reduce_strip<n>(p, mode, D, sub);
@@ -99,6 +111,9 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     // the column's reduced pixels live in the object row-cost array, which
     // solve_column writes only after its last read of them
     int16_t* const qs = reinterpret_cast<int16_t*>(lds.crow_o);
+    // per wave: one row of the object cost table while its prefix row is
+    // built, and a zero (the cost of an invalid pixel) after it
+    __shared__ float ostage[W][64 * NCH + 4];
     __shared__ int task_slot;
     __shared__ int red[3][W];
     const int lane = threadIdx.x & 63;
@@ -203,7 +218,8 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         float* PS = ws + stride;
         float* PA = ws + 2 * stride;
         float* PN = ws + 3 * stride;
-        float* PO = ws + 4 * stride;
+        float* PO = ws + slot_rows_offset(H);
+        const int pstride = (int)slot_row_floats(H);
         const int nsl = (H + 63) >> 6;
         auto q_at = [&](int c) {
             const int v = 64 * c + lane;
@@ -246,56 +262,57 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             t2 = __builtin_amdgcn_s_memtime();
 #endif
         }
-        const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
-        // the column's object rows, stored through one buffer resource with a
-        // per-lane offset and the row's offset in a scalar register
-        const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
-        // Byte offset of each slot's pixel within an object-cost row (2^30
-        // for an invalid pixel or a row past H: in the per-lane offset, which
-        // the bounds check always covers, so such lanes read 0); a row's
-        // offset is then the scalar part of every load.
-        uint32_t qoff[S];
+        // The object rows f = fmin + wave, fmin + wave + W, ...: row f of the
+        // object cost table (costs of mean f for every pixel disparity) is
+        // staged in LDS with a few coalesced loads; lane l then takes the
+        // costs of rows 256u + 4l .. 256u + 4l + 3 from it (a zero for an
+        // invalid pixel or a row past H), sums them in order, adds the wave
+        // scan of the lanes' sums and stores its four prefixes with one
+        // aligned 16-byte store.  The next row's loads are in flight while a
+        // row is scanned.
+        constexpr int U = (64 * S + 255) / 256;     // 256-row groups
+        constexpr int NST = 64 * NCH;               // staged costs per row
+        float* const stg = ostage[wave];
+        if (lane == 0) stg[NST] = 0.0f;
+        int qi[U][4];                               // index of each row's cost in the stage
 #pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const int x = q_at(c);
-            qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = 256 * u + 4 * lane + i;
+                const int x = (v < H) ? (int)qs[v] : -1;
+                qi[u][i] = (x >= 0) ? x : NST;
+            }
         }
-        // With several waves per column the loads of row f + W are in flight
-        // while row f is scanned; one-wave workgroups have no registers to
-        // spare for it (measured: double buffering made them spill and run
-        // slower) and load each row just before scanning it.
-        constexpr bool DB = (W > 1);
-        float oc[S], on[S];
-        auto load_row = [&](float (&o)[S], int f) {
+        const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+        const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)pstride * 4u);
+        float onext[NCH];
+        auto load_costs = [&](int f) {
             const uint32_t rowb = (uint32_t)(f * D) * 4u;
 #pragma unroll
-            for (int c = 0; c < S; ++c) o[c] = buf_load_b(otr, qoff[c], rowb);
+            for (int c = 0; c < NCH; ++c) onext[c] = buf_load_b(otr, (uint32_t)(64 * c + lane) * 4u, rowb);
         };
-        if constexpr (DB) {
-            if (fmin + wave <= fmax) load_row(oc, fmin + wave);
-        }
+        if (fmin + wave <= fmax) load_costs(fmin + wave);
 #pragma unroll 1
         for (int f = fmin + wave; f <= fmax; f += W) {
-            if constexpr (DB) {
-                if (f + W <= fmax) load_row(on, f + W);
-            } else {
-                load_row(oc, f);
-            }
-            const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)stride * 4u;
-            if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
-            // slots past H load zeros and store nothing: no per-slot branch,
-            // so the slots' scans can interleave
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) stg[64 * c + lane] = onext[c];
+            if (f + W <= fmax) load_costs(f + W);
+            const uint32_t rowoff = (uint32_t)(f - fmin) * (uint32_t)pstride * 4u;
+            if (lane == 0) buf_store_b(pow_, 0.0f, 12u, rowoff);
             float carry = 0.0f;
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-                const int v = 64 * c + lane;
-                const float o = wave_inclusive_scan(oc[c]) + carry;
-                if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
-                carry = readlane_f(o, 63);
-            }
-            if constexpr (DB) {
-#pragma unroll
-                for (int c = 0; c < S; ++c) oc[c] = on[c];
+            for (int u = 0; u < U; ++u) {
+                if (256 * u >= H) break;
+                const float o0 = stg[qi[u][0]], o1 = stg[qi[u][1]];
+                const float o2 = stg[qi[u][2]], o3 = stg[qi[u][3]];
+                const float a1 = o0 + o1, a2 = a1 + o2, a3 = a2 + o3;
+                const float incl = wave_inclusive_scan(a3);
+                const float e = (incl - a3) + carry;
+                const float r0 = e + o0, r1 = e + a1, r2 = e + a2, r3 = e + a3;
+                if (256 * u + 4 * lane < H)
+                    buf_store_b4(pow_, r0, r1, r2, r3, (uint32_t)(1024 * u + 16 * lane + 16), rowoff);
+                carry = readlane_f(incl, 63) + carry;
             }
         }
         __syncthreads();   // the tables written above are read back below, by every wave
@@ -309,7 +326,8 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         in.PS = PS;
         in.PA = PA;
         in.PN2 = PN;
-        in.PO = PO;
+        in.PO = PO + 3;
+        in.po_stride = pstride;
         in.fbase = fmin;
         in.fmax = fmax;
         in.q = qs;

@@ -42,8 +42,9 @@ struct ColumnIn {
     const float* PS;        // [H+1] sky cost prefix
     const float* PA;        // [H+1] prefix of 2*q+1 over valid pixels
     const float* PN2;       // [H+1] prefix of 2 over valid pixels
-    const float* PO;        // [fmax-fbase+1][H+1] object cost prefix, row f-fbase
+    const float* PO;        // [fmax-fbase+1][po_stride] object cost prefix, row f-fbase
     int fbase, fmax;        // disparity rows of PO (fbase = 0 if the column has an invalid pixel)
+    int po_stride = 0;      // floats from one PO row to the next (0: H+1)
     const int16_t* q;       // [H] reduced disparities of the column (LDS), -1 invalid
     const float* O_df;      // [D][D] object cost, row d (pixel disparity), column f (mean)
     int D;
@@ -117,9 +118,10 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
     const int lane = threadIdx.x & 63;
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
+    const int pstride = in.po_stride ? in.po_stride : stride;
     const int fbase = in.fbase;
     const int nrow = in.fmax - fbase + 1;
-    const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
+    const auto po = make_rsrc(in.PO, (uint32_t)(nrow * pstride) * 4u);
     const auto pgr = make_rsrc(in.PG, stride4);
     const auto psr = make_rsrc(in.PS, stride4);
     const auto par = make_rsrc(in.PA, stride4);
@@ -159,7 +161,7 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
                 float d0;
                 if (cls == 0) {
                     f0 = rounded_mean(kA, kN, eps);
-                    d0 = buf_load(po, (f0 - fbase) * stride + kk);
+                    d0 = buf_load(po, (f0 - fbase) * pstride + kk);
                 } else {
                     d0 = (cls == 1) ? kG : kS;
                 }
@@ -199,8 +201,8 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
                         const int p = s * 64 + lane, bb = p + 1;
                         const int f = rounded_mean(kA - pa[i], kN - pn[i], eps);
                         fv[i] = f;
-                        dk[i] = buf_load(po, (f - fbase) * stride + kk);
-                        db[i] = buf_load(po, (f - fbase) * stride + bb);
+                        dk[i] = buf_load(po, (f - fbase) * pstride + kk);
+                        db[i] = buf_load(po, (f - fbase) * pstride + bb);
                         const int r = (p < k) ? H - 1 - bb : 0;
                         thi[i] = __builtin_bit_cast(int, buf_load(fgh, r));
                         tlo[i] = __builtin_bit_cast(int, buf_load(fgl, r));
@@ -443,13 +445,14 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int stride = H + 1;
     const uint32_t stride4 = (uint32_t)stride * 4u;
+    const uint32_t pstride4 = (uint32_t)(in.po_stride ? in.po_stride : stride) * 4u;
     const int fbase = in.fbase, fmax = in.fmax;
     const int nrow = fmax - fbase + 1;               // <= d_range <= 64 * NCH
-    const auto po = make_rsrc(in.PO, (uint32_t)nrow * stride4);
+    const auto po = make_rsrc(in.PO, (uint32_t)nrow * pstride4);
     // object prefix entry at byte offset `off` of the column's table; the
     // LDS copy clamps the offset to the table (rows past the column's height
     // form arbitrary offsets), the buffer resource reads 0 past its end
-    const uint32_t po_last = (uint32_t)nrow * stride4 - 4u;
+    const uint32_t po_last = (uint32_t)nrow * pstride4 - 4u;
     auto po_at = [&](uint32_t off, uint32_t soff) -> float {
         if constexpr (POL) {
             return po_lds[__builtin_elementwise_min(off + soff, po_last) >> 2];
@@ -492,7 +495,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         eA[t] = in.PA[kk];
         eN[t] = in.PN2[kk];
         const int fi = mean_index(eA[t], eN[t], cmean);
-        mO[t] = po_at(__umul24((uint32_t)fi, stride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
+        mO[t] = po_at(__umul24((uint32_t)fi, pstride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
         fO[t] = fi;
     }
 
@@ -596,7 +599,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
 #pragma unroll
         for (int t = 0; t < SW; ++t) {
             const uint32_t fi = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, cmean);
-            pkP[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(t * 256));
+            pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
             fSP[t] = (int)fi;
         }
     }
@@ -687,7 +690,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 const int s = t * W + wave;
                 if (s < sj) continue;
                 const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
-                pk[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(s * 256));
+                pk[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(s * 256));
                 fS[t] = (int)fi;
             }
         };
@@ -804,7 +807,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 fO[t] = better ? fSP[t] : fO[t];
                 if constexpr (LINKS) bO[t] = better ? b : bO[t];
                 const uint32_t fi = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, cmean);
-                pkP[t] = po_at(__umul24(fi, stride4) + lane4, (uint32_t)(t * 256));
+                pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
                 fSP[t] = (int)fi;
             }
         } else if constexpr (EARLY) {

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void stage_frame_kernel(JobDesc job, JobDesc* 
 }
 
 size_t frame_fused_bytes(int ncols, int H, int D, int slots) {
-    const size_t stride = (size_t)(4 + D) * (size_t)(H + 1) * sizeof(float);
+    const size_t stride = (size_t)slot_floats(H, D) * sizeof(float);
     return kHeaderBytes + round256(sizeof(int2) * (size_t)ncols) + stride * (size_t)slots +
            kTableGuardBytes;
 }
@@ -42,7 +42,7 @@ hipError_t launch_frame_fused(const JobDesc& job, void* ws, size_t ws_bytes, int
     if (!f || job.ncols < 1) return hipErrorInvalidValue;
     const size_t base = frame_fused_bytes(job.ncols, job.H, job.D, 0);
     if (ws_bytes < base) return hipErrorInvalidValue;
-    long long stride = (long long)(4 + job.D) * (long long)(job.H + 1);
+    long long stride = slot_floats(job.H, job.D);
     const long long by_ws = (long long)((ws_bytes - base) / ((size_t)stride * sizeof(float)));
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 64 * waves, 0);

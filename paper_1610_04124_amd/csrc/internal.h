@@ -225,4 +225,13 @@ __device__ __forceinline__ void buf_store_b(__amdgpu_buffer_rsrc_t r, float x, u
                                           0);
 }
 
+// Four consecutive floats with one 16-byte store (voff + soff 16-byte aligned).
+__device__ __forceinline__ void buf_store_b4(__amdgpu_buffer_rsrc_t r, float x0, float x1, float x2,
+                                             float x3, uint32_t voff, uint32_t soff) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 v = {__builtin_bit_cast(uint32_t, x0), __builtin_bit_cast(uint32_t, x1),
+                     __builtin_bit_cast(uint32_t, x2), __builtin_bit_cast(uint32_t, x3)};
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, 0);
+}
+
 }  // namespace stx

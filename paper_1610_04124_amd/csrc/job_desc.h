@@ -41,7 +41,7 @@ inline JobDesc make_job_desc(const stixels_handle* h, const float* disp, int W, 
 // launch with a single job): a one-block staging kernel writes the job's
 // descriptor, its task list (column t is task t) and a zero task counter
 // into the workspace, then the persistent kernel runs with one scratch slot
-// of (4 + D)(h + 1) floats per resident workgroup.  No host-to-device copy
+// of slot_floats(h, D) floats per resident workgroup.  No host-to-device copy
 // and no allocation.  Workspace layout (ws 256-byte aligned):
 //   [0, 256)               descriptor
 //   [256, 512)             task counter
