@@ -58,22 +58,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, workgroups):
-    """HBM bytes per launch of the persistent kernel from the committed PMC
-    summary (one record per grid size the autotuner tries), if it was taken
-    on the current kernel sources and kernel variant and covers this number
-    of workgroups."""
+def profile_record(kernel, workgroups):
+    """HBM bytes per launch of the persistent kernel (and its VALU busy
+    fraction where taken) from the committed PMC summary, if it was taken on
+    the current kernel sources and kernel variant and covers this number of
+    workgroups: (bytes or None, busy or None)."""
     path = os.path.join(ROOT, "profiles", "batch_kernel_1024x440_b64_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         d = json.load(open(path))
     except Exception:
-        return None
+        return None, None
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel:
-        return None
+        return None, None
     rec = d.get("by_workgroups", {}).get(str(workgroups))
-    return rec.get("hbm_bytes_per_launch") if rec else None
+    busy = d.get("valu_busy_by_workgroups", {}).get(str(workgroups))
+    return (rec.get("hbm_bytes_per_launch") if rec else None), busy
 
 
 def percentile(xs, q):
@@ -646,13 +647,14 @@ def main():
     ops = OPS_PER_PAIR * pairs
     achieved = ops / avg_launch_s
     kernel = f"batch_kernel<7, 2, {waves}>" if columns == 1 else "batch_pair_kernel<7, 2>"
-    traffic = traffic_from_profiles(kernel, grid)
+    traffic, valu_busy = profile_record(kernel, grid)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 4),
                 "peak": round(VALU_PEAK / 1e12, 4), "unit": "TOP/s",
                 "frac": round(achieved / VALU_PEAK, 4), "traffic": traffic,
                 "kernel": kernel, "ops_per_pair": OPS_PER_PAIR, "pairs_per_launch": pairs,
                 "ops_per_launch": ops, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                 "frac_7op": round(OPS_SEPARABLE * pairs / avg_launch_s / VALU_PEAK, 4),
+                "valu_busy_counters": valu_busy,
                 "sclk_mhz_at_start": sclk}
 
     # ---------------- per-frame paths
