@@ -467,7 +467,7 @@ def cpu_baseline(frames, params, seconds_all=12.0, seconds_one=10.0):
     fps1, _, n1, dt1 = out["one"]
     return {"value": round(fps, 3), "unit": "frames/s", "cores": nt, "kind": "oracle",
             "sample": f"{n} of the {FRAMES} 1024x440 frames (seeds 0..{n - 1}), C FP64 oracle, "
-                      f"OpenMP over columns, {dt:.2f} s wall",
+                      f"OpenMP over columns, {dt:.2f} s wall ({dt * nt:.0f} core-seconds)",
             "one_core": {"value": round(fps1, 3), "unit": "frames/s", "cores": 1,
                          "sample": f"{n1} frames, {dt1:.2f} s wall"},
             "cpu_model": cpu_model()}
