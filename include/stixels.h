@@ -196,8 +196,8 @@ int stixels_compute(stixels_handle *h, const float *d_disparity, int32_t width, 
  * handle's workspace, so it also runs on STIXELS_FLAG_BATCH_ONLY handles.
  * Arguments and output as stixels_compute; the handle's camera pose only.
  * The handle's device must be current.  Frames whose descriptor, task list
- * and one scratch slot (4 (height + 1) + bins * round_up(height + 7, 4)
- * floats, rounded up to a multiple of 4) exceed the array
+ * and one scratch slot (the four small prefix tables and room for the
+ * object prefix table, about (bins + 1) * (height + 7) floats) exceed the array
  * return STIXELS_E_RANGE (no valid handle reaches that); a frame with more
  * columns than the array has slots runs on fewer workgroups.  Allocates
  * nothing.  Every call on one GPU shares that GPU's array, so calls that

@@ -63,8 +63,18 @@ enum PhaseSlot {
 __host__ __device__ constexpr long long slot_row_floats(int H) { return ((H + 10) / 4) * 4; }
 __host__ __device__ constexpr long long slot_rows_offset(int H) { return ((4LL * (H + 1) + 3) / 4) * 4; }
 __host__ __device__ constexpr long long slot_floats(int H, int D) {
-    return slot_rows_offset(H) + (long long)D * slot_row_floats(H);
+    // the full table (D rows of slot_row_floats) or the banded one (per
+    // 64-row slot at most D rows and the +inf row, 64 floats each)
+    return slot_rows_offset(H) + ((long long)D * slot_row_floats(H) > 64LL * ((H + 63) / 64) * (D + 1)
+                                      ? (long long)D * slot_row_floats(H)
+                                      : 64LL * ((H + 63) / 64) * (D + 1));
 }
+
+// One-wave columns of up to 8 slots keep a banded object prefix table
+// (solve_column's BAND): costs on the grid only (the recurrence with links
+// for costs off the grid keeps the full table).
+template <int S, int W, bool LINKS>
+constexpr bool kBanded = (W == 1) && (S <= 8) && !LINKS;
 
 __device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D, int sub) {
     switch (s) {
@@ -114,6 +124,9 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     // per wave: one row of the object cost table while its prefix row is
     // built, and a zero (the cost of an invalid pixel) after it
     __shared__ float ostage[W][64 * NCH + 4];
+    constexpr bool BAND = kBanded<S, W, LINKS>;
+    // BAND, per slot: first and last mean of its band, float offset of its rows
+    __shared__ int band_lo[S], band_hi[S], band_base[S];
     __shared__ int task_slot;
     __shared__ int red[3][W];
     const int lane = threadIdx.x & 63;
@@ -262,6 +275,115 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             t2 = __builtin_amdgcn_s_memtime();
 #endif
         }
+        uint32_t po_bytes = 0;
+        if constexpr (BAND) {
+            // Bands: a stixel [b, k] with k in slot t and a valid pixel has a
+            // mean between the smallest and the largest of (a) the valid
+            // pixels of slot t and (b) the means of the stixels [b', 64t-1]
+            // (b' < 64 t) with a valid pixel: its mean is a weighted average
+            // of the mean of its part below the slot and that of its part in
+            // the slot, and rounding is monotone.
+            __syncthreads();   // wave 0's prefix tables are read back below
+            int glo = INT_MAX, ghi = -1, base = 0;
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                if (64 * t >= H) {
+                    // padding: the recurrence's reads of this slot stay in range
+                    if (lane == 0) {
+                        band_lo[t] = fmin;
+                        band_hi[t] = -1;
+                        band_base[t] = 0;
+                    }
+                    continue;
+                }
+                const int x = q_at(t);
+                int lo = (x >= 0) ? x : INT_MAX, hi = x;
+                if (t > 0) {
+                    const float ax = PA[64 * t], nx = PN[64 * t];
+                    for (int c = 0; c < t; ++c) {
+                        const int b0 = 64 * c + lane;
+                        const float n2 = nx - PN[b0];
+                        if (n2 != 0.0f) {
+                            const int f = mean_index(ax - PA[b0], n2, J.prior.mean_eps);
+                            lo = min(lo, f);
+                            hi = max(hi, f);
+                        }
+                    }
+                }
+                lo = wave_min_i(lo);
+                hi = wave_max_i(hi);
+                if (hi < 0) lo = hi = fmin;     // no valid pixel reaches the slot
+                lo = __builtin_amdgcn_readfirstlane(lo);
+                hi = __builtin_amdgcn_readfirstlane(hi);
+                if (lane == 0) {
+                    band_lo[t] = lo;
+                    band_hi[t] = hi;
+                    band_base[t] = base;
+                }
+                // the +inf row (stixels without a valid pixel read it)
+                buf_store_b(make_rsrc(PO, 0x7ffffff0u), inf_f(), (uint32_t)(base + lane) * 4u, 0u);
+                base += (hi - lo + 2) * 64;
+                glo = min(glo, lo);
+                ghi = max(ghi, hi);
+            }
+            po_bytes = (uint32_t)base * 4u;
+            __syncthreads();
+            // Object rows f in [glo, ghi]: the full prefix over the column is
+            // scanned as in the full table, but a lane stores its four
+            // prefixes only where f lies in its slot's band, at row
+            // f - lo + 1 of the band.
+            constexpr int U = (64 * S + 255) / 256;
+            constexpr int NST = 64 * NCH;
+            float* const stg = ostage[0];
+            if (lane == 0) stg[NST] = 0.0f;
+            int qi[U][4];
+            int slo[U], shi[U], sbase[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int v = 256 * u + 4 * lane + i;
+                    const int x = (v < H) ? (int)qs[v] : -1;
+                    qi[u][i] = (x >= 0) ? x : NST;
+                }
+                const int t = min(4 * u + (lane >> 4), S - 1);
+                const bool real = (256 * u + 4 * lane) < 64 * S;
+                slo[u] = band_lo[t];
+                shi[u] = real ? band_hi[t] : -1;
+                // float offset of entry (mean f, position 4 (lane mod 16)) is
+                // sbase + 64 f: the band's rows start one row below mean lo
+                sbase[u] = band_base[t] + 64 * (1 - band_lo[t]) + 4 * (lane & 15);
+            }
+            const auto otr = make_rsrc(J.object_t, (uint32_t)(D * D) * 4u);
+            const auto pow_ = make_rsrc(PO, po_bytes);
+            float onext[NCH];
+            auto load_costs = [&](int f) {
+                const uint32_t rowb = (uint32_t)(f * D) * 4u;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) onext[c] = buf_load_b(otr, (uint32_t)(64 * c + lane) * 4u, rowb);
+            };
+            load_costs(glo);
+#pragma unroll 1
+            for (int f = glo; f <= ghi; ++f) {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) stg[64 * c + lane] = onext[c];
+                if (f + 1 <= ghi) load_costs(f + 1);
+                float carry = 0.0f;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (256 * u >= H) break;
+                    const float o0 = stg[qi[u][0]], o1 = stg[qi[u][1]];
+                    const float o2 = stg[qi[u][2]], o3 = stg[qi[u][3]];
+                    const float a1 = o0 + o1, a2 = a1 + o2, a3 = a2 + o3;
+                    const float incl = wave_inclusive_scan(a3);
+                    const float e = (incl - a3) + carry;
+                    const float r0 = e + o0, r1 = e + a1, r2 = e + a2, r3 = e + a3;
+                    if (f >= slo[u] && f <= shi[u])
+                        buf_store_b4(pow_, r0, r1, r2, r3, (uint32_t)(sbase[u] + 64 * f) * 4u, 0u);
+                    carry = readlane_f(incl, 63) + carry;
+                }
+            }
+        } else {
         // The object rows f = fmin + wave, fmin + wave + W, ...: row f of the
         // object cost table (costs of mean f for every pixel disparity) is
         // staged in LDS with a few coalesced loads; lane l then takes the
@@ -315,6 +437,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
                 carry = readlane_f(incl, 63) + carry;
             }
         }
+        }
         __syncthreads();   // the tables written above are read back below, by every wave
 #ifdef STX_PHASE_TIMING
         const unsigned long long t3 = __builtin_amdgcn_s_memtime();
@@ -326,8 +449,15 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
         in.PS = PS;
         in.PA = PA;
         in.PN2 = PN;
-        in.PO = PO + 3;
-        in.po_stride = pstride;
+        if constexpr (BAND) {
+            in.PO = PO;
+            in.band_lo = band_lo;
+            in.band_base = band_base;
+            in.po_bytes = po_bytes;
+        } else {
+            in.PO = PO + 3;
+            in.po_stride = pstride;
+        }
         in.fbase = fmin;
         in.fmax = fmax;
         in.q = qs;
@@ -346,7 +476,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
 #ifdef STX_PHASE_TIMING
         out.t_rec_end = &t_rec_end;
 #endif
-        solve_column<S, NCH, W, false, true, LINKS>(H, J.vtop, J.prior, in, out, lds);
+        solve_column<S, NCH, W, false, true, LINKS, BAND>(H, J.vtop, J.prior, in, out, lds);
 #ifdef STX_PHASE_TIMING
         if (threadIdx.x == 0) {
             __builtin_amdgcn_s_waitcnt(0);

@@ -45,6 +45,12 @@ struct ColumnIn {
     const float* PO;        // [fmax-fbase+1][po_stride] object cost prefix, row f-fbase
     int fbase, fmax;        // disparity rows of PO (fbase = 0 if the column has an invalid pixel)
     int po_stride = 0;      // floats from one PO row to the next (0: H+1)
+    // banded object prefix table (solve_column with BAND): per 64-row slot t,
+    // the first mean band_lo[t] of its band and the float offset band_base[t]
+    // of its rows within PO (LDS arrays)
+    const int* band_lo = nullptr;
+    const int* band_base = nullptr;
+    uint32_t po_bytes = 0;  // bytes of the PO table (0: its rows times po_stride)
     const int16_t* q;       // [H] reduced disparities of the column (LDS), -1 invalid
     const float* O_df;      // [D][D] object cost, row d (pixel disparity), column f (mean)
     int D;
@@ -71,7 +77,7 @@ struct LinkRows<S, true> {
 // per wave: 64 per disparity chunk).
 template <int S, int W, int QT = 256, bool LINKS = false>
 struct ColumnLds {
-    float qtab[W][QT];      // per wave: prior minus PO[f][b] over the disparity rows
+    float qtab[W][QT + 4];  // per wave: prior minus PO[f][b] over the disparity rows (from +4)
     float crow_g[64 * S];   // final GR^k of every row
     float crow_s[64 * S];   // final SK^k
     float crow_o[64 * S];   // final OB^k
@@ -112,7 +118,11 @@ __device__ __forceinline__ float pick3(float a0, float a1, float a2, int c) {
 // Backtracking of one column (Sec. 3.3, Sec. 4.4) by one wave64: every
 // row's final object, ground and sky cost and best object mean are in LDS
 // (L.crow_*), its prefix values in the column's tables (in).
-template <int S, class Lds>
+// BAND: the column's object prefix table is banded (solve_column), so the
+// object data terms are taken from the full prefix row of the stored mean of
+// the row's best object stixel, recomputed here (the first optimal candidate
+// has that mean).
+template <int S, class Lds, bool BAND = false>
 __device__ __forceinline__ void backtrack_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                                  const ColumnOut& out, const Lds& L) {
     const int lane = threadIdx.x & 63;
@@ -142,6 +152,28 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
     // stixels in lane registers (stixel t in lane t) and only counts the
     // rest; direct = true writes every stixel straight to its bottom-up
     // position (second pass, needed only for more than 64 stixels).
+    // BAND: R[s] = full object prefix of mean fr at entry 64 s + lane + 1
+    float R[BAND ? S : 1];
+    int fr = -1;
+    auto prefix_row = [&](int f) {
+        const auto odf = make_rsrc(in.O_df, (uint32_t)(in.D * in.D) * 4u);
+        float carry = 0.0f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int v = 64 * s + lane;
+            // the pixel of row v from the integer prefixes (2q+1 and 2 per valid pixel)
+            float o = 0.0f;
+            if (v < H) {
+                const float n2 = buf_load(pnr, v + 1) - buf_load(pnr, v);
+                const float a = buf_load(par, v + 1) - buf_load(par, v);
+                if (n2 != 0.0f) o = buf_load(odf, ((int)a >> 1) * in.D + f);
+            }
+            const float r = wave_inclusive_scan(o) + carry;
+            R[s] = r;
+            carry = readlane_f(r, 63);
+        }
+        fr = f;
+    };
     auto walk = [&](bool direct, int n_total, RecRegs& rr) -> int {
         int k = ktop, cls = ctop, t = 0;
         float target = total;
@@ -156,16 +188,35 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
             const float tO = pick3(P.trans[0][0], P.trans[0][1], P.trans[0][2], cls);
             const float tG = pick3(P.trans[1][0], P.trans[1][1], P.trans[1][2], cls);
             const float tS = pick3(P.trans[2][0], P.trans[2][1], P.trans[2][2], cls);
+            // BAND: the full prefix row of the stored mean of row k's best
+            // object stixel, and its entry at k+1
+            int fstar = 0;
+            float rk = 0.0f;
+            if constexpr (BAND) {
+                if (cls == 0) {
+                    fstar = (int)L.crow_f[k] + fbase;
+                    if (fstar != fr) prefix_row(fstar);
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (s == (k >> 6)) rk = readlane_f(R[s], k & 63);
+                }
+            }
             {   // bottom stixel b = 0 (prefix entries at 0 are zero)
                 int f0 = 0;
                 float d0;
+                bool ok = true;
                 if (cls == 0) {
                     f0 = rounded_mean(kA, kN, eps);
-                    d0 = buf_load(po, (f0 - fbase) * pstride + kk);
+                    if constexpr (BAND) {
+                        d0 = rk;
+                        ok = (f0 == fstar);
+                    } else {
+                        d0 = buf_load(po, (f0 - fbase) * pstride + kk);
+                    }
                 } else {
                     d0 = (cls == 1) ? kG : kS;
                 }
-                if (d0 + pick3(P.first[0], P.first[1], P.first[2], cls) == target) {
+                if (ok && d0 + pick3(P.first[0], P.first[1], P.first[2], cls) == target) {
                     lb = 0;
                     lf = f0;
                 }
@@ -201,8 +252,13 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
                         const int p = s * 64 + lane, bb = p + 1;
                         const int f = rounded_mean(kA - pa[i], kN - pn[i], eps);
                         fv[i] = f;
-                        dk[i] = buf_load(po, (f - fbase) * pstride + kk);
-                        db[i] = buf_load(po, (f - fbase) * pstride + bb);
+                        if constexpr (BAND) {
+                            dk[i] = rk;
+                            db[i] = R[s];          // entry p+1 = 64 s + lane + 1
+                        } else {
+                            dk[i] = buf_load(po, (f - fbase) * pstride + kk);
+                            db[i] = buf_load(po, (f - fbase) * pstride + bb);
+                        }
                         const int r = (p < k) ? H - 1 - bb : 0;
                         thi[i] = __builtin_bit_cast(int, buf_load(fgh, r));
                         tlo[i] = __builtin_bit_cast(int, buf_load(fgl, r));
@@ -230,7 +286,10 @@ __device__ __forceinline__ void backtrack_column(const int H, const int vtop, co
                     const float co = mo + tO + pen_o + data;
                     const float cg = mg + tG + pen_g + data;
                     const float cs = ms + tS + data;
-                    const int code = !inr ? 3
+                    // BAND: an object candidate whose mean is not the stored one
+                    // is not the first optimal one
+                    const bool skip = !inr || (BAND && cls == 0 && f != fstar);
+                    const int code = skip ? 3
                                    : (co == target ? 0 : (cg == target ? 1 : (cs == target ? 2 : 3)));
                     const uint64_t m = __ballot(code < 3);
                     if (m) {
@@ -434,8 +493,16 @@ __device__ __forceinline__ void backtrack_links(const int H, const int vtop, con
 // load at each slot boundary; a column alone on its SIMD keeps the per-step
 // prefetch).  LINKS: also keep the cut position of every row's best stixel
 // per class (one select per candidate) and backtrack along those links, for
-// costs off the grid.  On return the results are written.
-template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false>
+// costs off the grid.  BAND (one-wave columns of up to 8 slots): the object
+// prefix table holds, per 64-row slot t, only the rows of the means that a
+// stixel ending in the slot can take, [band_lo[t], band_hi[t]], after one row
+// of +inf: row r of slot t is mean band_lo[t] + r - 1, entry 64 t + l + 1 at
+// float l.  The mean index of a candidate is then relative to its slot's
+// band; a stixel without valid pixels (mean 0, index 0) reads the +inf row
+// and is folded separately with its exact cost.  On return the results are
+// written.
+template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false,
+          bool BAND = false>
 __device__ __forceinline__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                              const ColumnOut& out, ColumnLds<S, W, 64 * NCH, LINKS>& L,
                              const float* po_lds = nullptr) {
@@ -448,7 +515,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     const uint32_t pstride4 = (uint32_t)(in.po_stride ? in.po_stride : stride) * 4u;
     const int fbase = in.fbase, fmax = in.fmax;
     const int nrow = fmax - fbase + 1;               // <= d_range <= 64 * NCH
-    const auto po = make_rsrc(in.PO, (uint32_t)nrow * pstride4);
+    const auto po = make_rsrc(in.PO, in.po_bytes ? in.po_bytes : (uint32_t)nrow * pstride4);
     // object prefix entry at byte offset `off` of the column's table; the
     // LDS copy clamps the offset to the table (rows past the column's height
     // form arbitrary offsets), the buffer resource reads 0 past its end
@@ -466,7 +533,14 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
     const auto pgr = make_rsrc(in.PG, stride4);
     const auto psr = make_rsrc(in.PS, stride4);
-    float* const qtab = L.qtab[wave];
+    float* const qtab = L.qtab[wave] + 4;
+    static_assert(!BAND || (W == 1 && S <= 8 && !LINKS), "banded tables: one-wave short columns");
+    // BAND, per slot t: the mean-index constant of its band (index = mean -
+    // band_lo[t] + 1), its rows' byte offset within PO and the byte offset,
+    // within the prior table, of index 0 (mean band_lo[t] - 1)
+    float bcm[BAND ? SW : 1];
+    uint32_t bsb[BAND ? SW : 1];
+    int bqo[BAND ? SW : 1];
 
     // local slot t of this wave is global slot t W + wave
     float eA[SW], eN[SW];               // prefix values at k+1 (mean numerator, 2 n)
@@ -478,6 +552,17 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     // taller ones, or the last slot of a wave when W does not divide S) are
     // padding: their rows are never read.
     const int nslots = (H + 63) >> 6;
+
+    if constexpr (BAND) {
+#pragma unroll
+        for (int t = 0; t < SW; ++t) {
+            const int lo = __builtin_amdgcn_readfirstlane(in.band_lo[t]);
+            bcm[t] = P.mean_eps - (float)(lo - 1);
+            bsb[t] = (uint32_t)__builtin_amdgcn_readfirstlane(in.band_base[t]) * 4u;
+            bqo[t] = (lo - 1 - fbase) * 4;
+        }
+    }
+    const uint32_t lane4b = (uint32_t)lane * 4u;     // entry 64 t + lane + 1 of a band row
 
     // Bottom-stixel candidates (b = 0): data(0, k) + F[c] + beta.
 #pragma unroll
@@ -494,9 +579,18 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         const int kk = min(k + 1, H);
         eA[t] = in.PA[kk];
         eN[t] = in.PN2[kk];
-        const int fi = mean_index(eA[t], eN[t], cmean);
-        mO[t] = po_at(__umul24((uint32_t)fi, pstride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
-        fO[t] = fi;
+        if constexpr (BAND) {
+            // mean 0 (no valid pixel in rows 0..k) has data cost 0; fO holds
+            // byte offsets (mean - fbase) * 4 into the prior table
+            const uint32_t fr = (uint32_t)mean_index(eA[t], eN[t], bcm[t]);
+            const float d = po_at((fr << 8) + lane4b, bsb[t]);
+            mO[t] = ((eN[t] == 0.0f) ? 0.0f : d) + P.first[0];
+            fO[t] = (eN[t] == 0.0f) ? 0 : (int)(fr << 2) + bqo[t];
+        } else {
+            const int fi = mean_index(eA[t], eN[t], cmean);
+            mO[t] = po_at(__umul24((uint32_t)fi, pstride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
+            fO[t] = fi;
+        }
     }
 
     // The object prefix column at the current base, PO[fbase + 64c + lane][b],
@@ -598,9 +692,15 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         const float nA0 = readlane_f(eA[0], 0), nN0 = readlane_f(eN[0], 0);
 #pragma unroll
         for (int t = 0; t < SW; ++t) {
-            const uint32_t fi = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, cmean);
-            pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
-            fSP[t] = (int)fi;
+            if constexpr (BAND) {
+                const uint32_t fr = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, bcm[t]);
+                pkP[t] = po_at((fr << 8) + lane4b, bsb[t]);
+                fSP[t] = (int)(fr << 2) + bqo[t];
+            } else {
+                const uint32_t fi = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, cmean);
+                pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
+                fSP[t] = (int)fi;
+            }
         }
     }
 
@@ -746,7 +846,8 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         const int tlo = BLK ? readlane_i(blk.tlo, jl) : tlo_n;
         // pixel q_{j+1}, base b+1 (b <= H-1); tall columns read the pixel
         // from LDS (registers held across their runtime loop spill)
-        load_next(b, QB ? readlane_i(blk.q, jl) : (int)in.q[b]);
+        const int qb = QB ? readlane_i(blk.q, jl) : (int)in.q[b];   // pixel q_b
+        load_next(b, qb);
 
         const float XS =
             vmin(vmin(Co + P.trans[0][2], Cg + P.trans[1][2]), Cs + P.trans[2][2]) - bS;
@@ -754,7 +855,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         RS = vmin(RS, XS);
         const float Xoo = Co + P.trans[0][0];
         const float Xoo_p = Xoo + P.c_ord;
-        const int tord = fp + fbase + P.tau_ord;
+        const int tord = (BAND ? (fp >> 2) : fp) + fbase + P.tau_ord;
         const float Xso = Cs + P.trans[2][0];
         float XG = INF, Xgo = INF, Xgo_d = INF, Xgo_g = INF;
         if constexpr (GR) {
@@ -794,7 +895,12 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
 #pragma unroll
             for (int t = 0; t < SW; ++t) {
                 if (t < sj) continue;
-                qv[t] = qtab[(uint32_t)fSP[t] & (64u * NCH - 1u)];
+                if constexpr (BAND) {
+                    // byte offset (mean - fbase) * 4 >= -4: the table's padding
+                    qv[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(qtab) + fSP[t]);
+                } else {
+                    qv[t] = qtab[(uint32_t)fSP[t] & (64u * NCH - 1u)];
+                }
             }
 #pragma unroll
             for (int t = 0; t < SW; ++t) {
@@ -806,9 +912,42 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 mO[t] = better ? cO : mO[t];
                 fO[t] = better ? fSP[t] : fO[t];
                 if constexpr (LINKS) bO[t] = better ? b : bO[t];
-                const uint32_t fi = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, cmean);
-                pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
-                fSP[t] = (int)fi;
+                if constexpr (BAND) {
+                    const uint32_t fr = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, bcm[t]);
+                    pkP[t] = po_at((fr << 8) + lane4b, bsb[t]);
+                    fSP[t] = (int)(fr << 2) + bqo[t];
+                } else {
+                    const uint32_t fi = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, cmean);
+                    pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
+                    fSP[t] = (int)fi;
+                }
+            }
+            if constexpr (BAND) {
+                // stixels [b, k] without a valid pixel (pixel b invalid, n = 0):
+                // mean 0, data cost 0, cost the prior at mean 0 (fbase is 0
+                // whenever the column holds an invalid pixel); their gathers
+                // read the +inf row, so they are folded here
+                if (qb < 0) {
+                    const float v1 = (0 > tord) ? Xoo_p : Xoo;
+                    float pr0;
+                    if constexpr (GR) {
+                        float v2 = (0 < tlo) ? Xgo_g : Xgo;
+                        v2 = (0 > thi) ? Xgo_d : v2;
+                        pr0 = vmin(vmin(v1, v2), Xso);
+                    } else {
+                        pr0 = vmin(v1, Xso);
+                    }
+#pragma unroll
+                    for (int t = 0; t < SW; ++t) {
+                        if (t < sj) continue;
+                        // n = 0 <=> no valid pixel in rows b..k; pixel b is
+                        // invalid, so PN2 at b+1 (nN) equals PN2 at b
+                        const bool act = ((t > sj) || (lane > jl)) && (eN[t] == nN);
+                        const bool better = act && (pr0 < mO[t]);
+                        mO[t] = better ? pr0 : mO[t];
+                        fO[t] = better ? 0 : fO[t];
+                    }
+                }
             }
         } else if constexpr (EARLY) {
             if (group_open(0)) fold(0);
@@ -886,7 +1025,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         const int s = t * W + wave;
         if (s < S) {
             L.crow_o[s * 64 + lane] = mO[t];
-            L.crow_f[s * 64 + lane] = (uint8_t)fO[t];
+            L.crow_f[s * 64 + lane] = (uint8_t)(BAND ? (fO[t] >> 2) : fO[t]);
             if constexpr (LINKS) L.lk.b[0][s * 64 + lane] = (int16_t)bO[t];
         }
     }
@@ -899,7 +1038,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     if constexpr (LINKS) {
         backtrack_links<S>(H, vtop, P, in, out, L);
     } else {
-        backtrack_column<S>(H, vtop, P, in, out, L);
+        backtrack_column<S, ColumnLds<S, W, 64 * NCH, LINKS>, BAND>(H, vtop, P, in, out, L);
     }
 }
 

@@ -82,8 +82,8 @@ def test_two_calls_second_smaller_equal_compute_and_oracle():
 
 def test_batch_only_handle_and_fewer_slots_than_columns():
     # 2048x880, 256 disparities, s = 3: 682 columns, while the fixed
-    # workspace holds 72 scratch slots of 230,852 floats (the prefix tables
-    # and 256 object prefix rows of 888 floats)
+    # workspace holds 71 scratch slots of 233,796 floats (the prefix tables
+    # and room for the object prefix table's 256 rows)
     W, H, D = 2048, 880, 256
     kw = dict(camera=synth.camera_for_size(W, H), stixel_width=3, max_disparity=D, max_width=W,
               max_height=H)
