@@ -70,11 +70,11 @@ __host__ __device__ constexpr long long slot_floats(int H, int D) {
                                       : 64LL * ((H + 63) / 64) * (D + 1));
 }
 
-// One-wave columns of up to 8 slots keep a banded object prefix table
-// (solve_column's BAND): costs on the grid only (the recurrence with links
-// for costs off the grid keeps the full table).
+// The persistent kernel keeps a banded object prefix table (solve_column's
+// BAND) for costs on the grid; the recurrence with links for costs off the
+// grid keeps the full table.
 template <int S, int W, bool LINKS>
-constexpr bool kBanded = (W == 1) && (S <= 8) && !LINKS;
+constexpr bool kBanded = !LINKS;
 
 __device__ __forceinline__ int reduce_any(const float* p, int s, int mode, int D, int sub) {
     switch (s) {
@@ -126,7 +126,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     __shared__ float ostage[W][64 * NCH + 4];
     constexpr bool BAND = kBanded<S, W, LINKS>;
     // BAND, per slot: first and last mean of its band, float offset of its rows
-    __shared__ int band_lo[S], band_hi[S], band_base[S];
+    __shared__ int band_lo[S], band_hi[S], band_base[S], band_all[3];
     __shared__ int task_slot;
     __shared__ int red[3][W];
     const int lane = threadIdx.x & 63;
@@ -285,6 +285,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             // the slot, and rounding is monotone.
             __syncthreads();   // wave 0's prefix tables are read back below
             int glo = INT_MAX, ghi = -1, base = 0;
+            if (wave == 0) {
 #pragma unroll
             for (int t = 0; t < S; ++t) {
                 if (64 * t >= H) {
@@ -326,15 +327,26 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
                 glo = min(glo, lo);
                 ghi = max(ghi, hi);
             }
-            po_bytes = (uint32_t)base * 4u;
+            if (W > 1 && lane == 0) {
+                band_all[0] = glo;
+                band_all[1] = ghi;
+                band_all[2] = base;
+            }
+            }
             __syncthreads();
+            if constexpr (W > 1) {
+                glo = __builtin_amdgcn_readfirstlane(band_all[0]);
+                ghi = __builtin_amdgcn_readfirstlane(band_all[1]);
+                base = __builtin_amdgcn_readfirstlane(band_all[2]);
+            }
+            po_bytes = (uint32_t)base * 4u;
             // Object rows f in [glo, ghi]: the full prefix over the column is
             // scanned as in the full table, but a lane stores its four
             // prefixes only where f lies in its slot's band, at row
             // f - lo + 1 of the band.
             constexpr int U = (64 * S + 255) / 256;
             constexpr int NST = 64 * NCH;
-            float* const stg = ostage[0];
+            float* const stg = ostage[wave];
             if (lane == 0) stg[NST] = 0.0f;
             int qi[U][4];
             int slo[U], shi[U], sbase[U];
@@ -362,12 +374,12 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) onext[c] = buf_load_b(otr, (uint32_t)(64 * c + lane) * 4u, rowb);
             };
-            load_costs(glo);
+            if (W == 1 || glo + wave <= ghi) load_costs(glo + wave);   // glo <= ghi
 #pragma unroll 1
-            for (int f = glo; f <= ghi; ++f) {
+            for (int f = glo + wave; f <= ghi; f += W) {
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) stg[64 * c + lane] = onext[c];
-                if (f + 1 <= ghi) load_costs(f + 1);
+                if (f + W <= ghi) load_costs(f + W);
                 float carry = 0.0f;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {

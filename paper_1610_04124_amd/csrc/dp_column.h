@@ -493,7 +493,7 @@ __device__ __forceinline__ void backtrack_links(const int H, const int vtop, con
 // load at each slot boundary; a column alone on its SIMD keeps the per-step
 // prefetch).  LINKS: also keep the cut position of every row's best stixel
 // per class (one select per candidate) and backtrack along those links, for
-// costs off the grid.  BAND (one-wave columns of up to 8 slots): the object
+// costs off the grid.  BAND (costs on the grid): the object
 // prefix table holds, per 64-row slot t, only the rows of the means that a
 // stixel ending in the slot can take, [band_lo[t], band_hi[t]], after one row
 // of +inf: row r of slot t is mean band_lo[t] + r - 1, entry 64 t + l + 1 at
@@ -534,7 +534,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     const auto pgr = make_rsrc(in.PG, stride4);
     const auto psr = make_rsrc(in.PS, stride4);
     float* const qtab = L.qtab[wave] + 4;
-    static_assert(!BAND || (W == 1 && S <= 8 && !LINKS), "banded tables: one-wave short columns");
+    static_assert(!BAND || !LINKS, "banded tables: costs on the grid");
     // BAND, per slot t: the mean-index constant of its band (index = mean -
     // band_lo[t] + 1), its rows' byte offset within PO and the byte offset,
     // within the prior table, of index 0 (mean band_lo[t] - 1)
@@ -556,9 +556,10 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     if constexpr (BAND) {
 #pragma unroll
         for (int t = 0; t < SW; ++t) {
-            const int lo = __builtin_amdgcn_readfirstlane(in.band_lo[t]);
+            const int sg = t * W + wave;                // global slot
+            const int lo = __builtin_amdgcn_readfirstlane(in.band_lo[sg]);
             bcm[t] = P.mean_eps - (float)(lo - 1);
-            bsb[t] = (uint32_t)__builtin_amdgcn_readfirstlane(in.band_base[t]) * 4u;
+            bsb[t] = (uint32_t)__builtin_amdgcn_readfirstlane(in.band_base[sg]) * 4u;
             bqo[t] = (lo - 1 - fbase) * 4;
         }
     }
@@ -789,9 +790,15 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
             for (int t = g0; t < g0 + G && t < SW; ++t) {
                 const int s = t * W + wave;
                 if (s < sj) continue;
-                const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
-                pk[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(s * 256));
-                fS[t] = (int)fi;
+                if constexpr (BAND) {
+                    const uint32_t fr = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, bcm[t]);
+                    pk[t] = po_at((fr << 8) + lane4b, bsb[t]);
+                    fS[t] = (int)(fr << 2) + bqo[t];
+                } else {
+                    const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
+                    pk[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(s * 256));
+                    fS[t] = (int)fi;
+                }
             }
         };
         auto fold = [&](int g0) {
@@ -799,8 +806,13 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
 #pragma unroll
             for (int t = g0; t < g0 + G && t < SW; ++t) {
                 if (t * W + wave < sj) continue;
-                // fi < 64 NCH except, possibly, in rows past H
-                qv[t] = qtab[(uint32_t)fS[t] & (64u * NCH - 1u)];
+                if constexpr (BAND) {
+                    // byte offset (mean - fbase) * 4 >= -4: the table's padding
+                    qv[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(qtab) + fS[t]);
+                } else {
+                    // fi < 64 NCH except, possibly, in rows past H
+                    qv[t] = qtab[(uint32_t)fS[t] & (64u * NCH - 1u)];
+                }
             }
 #pragma unroll
             for (int t = g0; t < g0 + G && t < SW; ++t) {
@@ -923,10 +935,8 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 }
             }
             if constexpr (BAND) {
-                // stixels [b, k] without a valid pixel (pixel b invalid, n = 0):
-                // mean 0, data cost 0, cost the prior at mean 0 (fbase is 0
-                // whenever the column holds an invalid pixel); their gathers
-                // read the +inf row, so they are folded here
+                // stixels [b, k] without a valid pixel: pixel b is invalid,
+                // so PN2 at b+1 (nN) equals PN2 at b
                 if (qb < 0) {
                     const float v1 = (0 > tord) ? Xoo_p : Xoo;
                     float pr0;
@@ -940,8 +950,6 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
 #pragma unroll
                     for (int t = 0; t < SW; ++t) {
                         if (t < sj) continue;
-                        // n = 0 <=> no valid pixel in rows b..k; pixel b is
-                        // invalid, so PN2 at b+1 (nN) equals PN2 at b
                         const bool act = ((t > sj) || (lane > jl)) && (eN[t] == nN);
                         const bool better = act && (pr0 < mO[t]);
                         mO[t] = better ? pr0 : mO[t];
@@ -951,6 +959,32 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
             }
         } else if constexpr (EARLY) {
             if (group_open(0)) fold(0);
+            if constexpr (BAND) {
+                // stixels [b, k] without a valid pixel (pixel b invalid, n = 0)
+                // have mean 0, data cost 0 and cost the prior at mean 0 (fbase
+                // is 0 whenever the column holds an invalid pixel); their
+                // gathers read the +inf row, so they are folded here
+                if (qb < 0) {
+                    const float v1 = (0 > tord) ? Xoo_p : Xoo;
+                    float pr0;
+                    if constexpr (GR) {
+                        float v2 = (0 < tlo) ? Xgo_g : Xgo;
+                        v2 = (0 > thi) ? Xgo_d : v2;
+                        pr0 = vmin(vmin(v1, v2), Xso);
+                    } else {
+                        pr0 = vmin(v1, Xso);
+                    }
+#pragma unroll
+                    for (int t = 0; t < SW; ++t) {
+                        const int s = t * W + wave;
+                        if (s < sj) continue;
+                        const bool act = ((s > sj) || (lane > jl)) && (eN[t] == bN);
+                        const bool better = act && (pr0 < mO[t]);
+                        mO[t] = better ? pr0 : mO[t];
+                        fO[t] = better ? 0 : fO[t];
+                    }
+                }
+            }
         } else {
 #pragma unroll
             for (int g0 = 0; g0 < SW; g0 += G) {
@@ -958,6 +992,32 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 if (!group_open(g0)) continue;
                 gather(g0);
                 fold(g0);
+            }
+            if constexpr (BAND) {
+                // stixels [b, k] without a valid pixel (pixel b invalid, n = 0)
+                // have mean 0, data cost 0 and cost the prior at mean 0 (fbase
+                // is 0 whenever the column holds an invalid pixel); their
+                // gathers read the +inf row, so they are folded here
+                if (qb < 0) {
+                    const float v1 = (0 > tord) ? Xoo_p : Xoo;
+                    float pr0;
+                    if constexpr (GR) {
+                        float v2 = (0 < tlo) ? Xgo_g : Xgo;
+                        v2 = (0 > thi) ? Xgo_d : v2;
+                        pr0 = vmin(vmin(v1, v2), Xso);
+                    } else {
+                        pr0 = vmin(v1, Xso);
+                    }
+#pragma unroll
+                    for (int t = 0; t < SW; ++t) {
+                        const int s = t * W + wave;
+                        if (s < sj) continue;
+                        const bool act = ((s > sj) || (lane > jl)) && (eN[t] == bN);
+                        const bool better = act && (pr0 < mO[t]);
+                        mO[t] = better ? pr0 : mO[t];
+                        fO[t] = better ? 0 : fO[t];
+                    }
+                }
             }
         }
     };
