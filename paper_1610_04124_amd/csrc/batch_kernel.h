@@ -103,10 +103,13 @@ __device__ __forceinline__ int wave_max_i(int x) {
 constexpr unsigned int kXcdStaggerCycles = 10000u;
 
 // Waves per SIMD the register allocation of each variant is held to (the
-// compiler's own choice leaves a few registers above the next step down;
-// multi-wave workgroups keep a little more room for the row broadcast).
+// compiler's own choice leaves a few registers above the next step down).
+// Columns of up to 7 slots per wave get 128 registers (4 waves per SIMD):
+// with the banded object prefix table, one-wave columns held to 96 (5 waves)
+// spilled more and measured 4 % slower.
 constexpr int batch_waves(int slots_per_wave, int waves) {
-    return slots_per_wave <= 7 ? (waves == 1 ? 5 : 4) : (slots_per_wave <= 14 ? 3 : 2);
+    (void)waves;
+    return slots_per_wave <= 7 ? 4 : (slots_per_wave <= 14 ? 3 : 2);
 }
 
 // One workgroup of W waves per column task.  LINKS: the recurrence keeps
