@@ -884,7 +884,9 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         // in order, so no barrier guards it)
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            if (c >= nchunk) break;
+            // two chunks are both built (one block, so that the compares and
+            // selects of the two interleave); an unused chunk is never read
+            if (NCH > 2 && c >= nchunk) break;
             const int f = fbase + 64 * c + lane;
             const float v1 = (f > tord) ? Xoo_p : Xoo;
             float pr;
