@@ -132,10 +132,20 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
     __shared__ int band_lo[S], band_hi[S], band_base[S], band_all[3];
     __shared__ int task_slot;
     __shared__ int red[3][W];
+    // one-wave banded columns of up to 8 slots: rcp(2 n) for n = 0 .. 64 S,
+    // read by the recurrence in place of a v_rcp_f32 per candidate (the same
+    // values; rcp(0) = +inf); written once per workgroup, before the first
+    // task's barriers
+    constexpr bool RT = BAND && W == 1 && S <= 8;
+    __shared__ float rtab[RT ? 64 * S + 1 : 1];
     const int lane = threadIdx.x & 63;
     const int wave = (W == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     float* ws = scratch + (size_t)blockIdx.x * (size_t)scratch_stride;
     (void)hmax;
+    if constexpr (RT) {
+        for (int n = threadIdx.x; n <= 64 * S; n += 64 * W)
+            rtab[n] = __builtin_amdgcn_rcpf((float)(2 * n));
+    }
 #ifdef STX_PHASE_TIMING
     // wave 0 stamps the shader clock at each phase boundary of a task
     const unsigned long long t_entry = __builtin_amdgcn_s_memtime();
@@ -469,6 +479,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
             in.band_lo = band_lo;
             in.band_base = band_base;
             in.po_bytes = po_bytes;
+            in.rtab = rtab;
         } else {
             in.PO = PO + 3;
             in.po_stride = pstride;
@@ -491,7 +502,7 @@ __attribute__((amdgpu_waves_per_eu(batch_waves((S + W - 1) / W, W)))) void batch
 #ifdef STX_PHASE_TIMING
         out.t_rec_end = &t_rec_end;
 #endif
-        solve_column<S, NCH, W, false, true, LINKS, BAND>(H, J.vtop, J.prior, in, out, lds);
+        solve_column<S, NCH, W, false, true, LINKS, BAND, RT>(H, J.vtop, J.prior, in, out, lds);
 #ifdef STX_PHASE_TIMING
         if (threadIdx.x == 0) {
             __builtin_amdgcn_s_waitcnt(0);

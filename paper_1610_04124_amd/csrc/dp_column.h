@@ -51,6 +51,9 @@ struct ColumnIn {
     const int* band_lo = nullptr;
     const int* band_base = nullptr;
     uint32_t po_bytes = 0;  // bytes of the PO table (0: its rows times po_stride)
+    // solve_column with RT: rcp(2 n) for n = 0 .. 64 S (LDS), the values
+    // v_rcp_f32 gives, read in place of that quarter-rate instruction
+    const float* rtab = nullptr;
     const int16_t* q;       // [H] reduced disparities of the column (LDS), -1 invalid
     const float* O_df;      // [D][D] object cost, row d (pixel disparity), column f (mean)
     int D;
@@ -499,10 +502,14 @@ __device__ __forceinline__ void backtrack_links(const int H, const int vtop, con
 // of +inf: row r of slot t is mean band_lo[t] + r - 1, entry 64 t + l + 1 at
 // float l.  The mean index of a candidate is then relative to its slot's
 // band; a stixel without valid pixels (mean 0, index 0) reads the +inf row
-// and is folded separately with its exact cost.  On return the results are
-// written.
+// and is folded separately with its exact cost.  RT: the reciprocal 1/(2n)
+// of a candidate's rounded mean comes from in.rtab (an LDS table of the
+// values v_rcp_f32 gives, so every mean is the same), the row counts are
+// kept as byte offsets n * 4 into it: one LDS read replaces a subtraction
+// and a v_rcp_f32, which issues at a quarter of the VALU rate.  On return
+// the results are written.
 template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false,
-          bool BAND = false>
+          bool BAND = false, bool RT = false>
 __device__ __forceinline__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
                              const ColumnOut& out, ColumnLds<S, W, 64 * NCH, LINKS>& L,
                              const float* po_lds = nullptr) {
@@ -528,8 +535,26 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         }
     };
     const float eps = P.mean_eps;
+    using NT = std::conditional_t<RT, int, float>;
     const float cmean = eps - (float)fbase;          // mean_index gives f - fbase
     const float INF = inf_f();
+    // rounded mean index from the prefix differences of the numerator and
+    // of the row count (2 n, or with RT its byte offset into the reciprocal
+    // table), and a row count read from a lane
+    const float* const rtab = in.rtab;
+    auto mean_of = [&](float a, NT nd, float c) -> int {
+        if constexpr (RT) {
+            const float r =
+                *reinterpret_cast<const float*>(reinterpret_cast<const char*>(rtab) + nd);
+            return cvt_i32_nan0(__builtin_fmaf(a, r, c));
+        } else {
+            return mean_index(a, nd, c);
+        }
+    };
+    auto readlane_n = [](NT v, int l) -> NT {
+        if constexpr (RT) return readlane_i(v, l);
+        else return readlane_f(v, l);
+    };
     const uint32_t lane4 = (uint32_t)(lane + 1) * 4u;   // byte offset of row k+1 within a slot
     const auto pgr = make_rsrc(in.PG, stride4);
     const auto psr = make_rsrc(in.PS, stride4);
@@ -543,7 +568,10 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     int bqo[BAND ? SW : 1];
 
     // local slot t of this wave is global slot t W + wave
-    float eA[SW], eN[SW];               // prefix values at k+1 (mean numerator, 2 n)
+    // prefix values at k+1: mean numerator and 2 n (RT: n * 4, a byte offset
+    // into the reciprocal table)
+    float eA[SW];
+    NT eN[SW];
     float mO[SW];                       // OB^k so far
     int fO[SW];                         // mean (- fbase) of the best object stixel ending at k
     int bO[LINKS ? SW : 1];             // its cut position (LINKS)
@@ -572,23 +600,28 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         if constexpr (LINKS) bO[t] = 0;
         if (s >= nslots) {
             mO[t] = INF;
-            eA[t] = eN[t] = 0.0f;
+            eA[t] = 0.0f;
+            eN[t] = 0;
             fO[t] = 0;
             continue;
         }
         const int k = s * 64 + lane;
         const int kk = min(k + 1, H);
         eA[t] = in.PA[kk];
-        eN[t] = in.PN2[kk];
+        if constexpr (RT) {
+            eN[t] = (int)in.PN2[kk] * 2;
+        } else {
+            eN[t] = in.PN2[kk];
+        }
         if constexpr (BAND) {
             // mean 0 (no valid pixel in rows 0..k) has data cost 0; fO holds
             // byte offsets (mean - fbase) * 4 into the prior table
-            const uint32_t fr = (uint32_t)mean_index(eA[t], eN[t], bcm[t]);
+            const uint32_t fr = (uint32_t)mean_of(eA[t], eN[t], bcm[t]);
             const float d = po_at((fr << 8) + lane4b, bsb[t]);
-            mO[t] = ((eN[t] == 0.0f) ? 0.0f : d) + P.first[0];
-            fO[t] = (eN[t] == 0.0f) ? 0 : (int)(fr << 2) + bqo[t];
+            mO[t] = ((eN[t] == 0) ? 0.0f : d) + P.first[0];
+            fO[t] = (eN[t] == 0) ? 0 : (int)(fr << 2) + bqo[t];
         } else {
-            const int fi = mean_index(eA[t], eN[t], cmean);
+            const int fi = mean_of(eA[t], eN[t], cmean);
             mO[t] = po_at(__umul24((uint32_t)fi, pstride4) + (uint32_t)kk * 4u, 0u) + P.first[0];
             fO[t] = fi;
         }
@@ -636,7 +669,8 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     struct Blk {
         int q = 0, thi = 0, tlo = 0;
         float ps = 0.0f, pg = 0.0f;
-        float na = 0.0f, nn = 0.0f;     // PA and PN2 at j+2 (PIPE)
+        float na = 0.0f;                // PA and PN2 (RT: as eN) at j+2 (PIPE)
+        NT nn = 0;
     };
     const auto par = make_rsrc(in.PA, stride4);
     const auto pnr = make_rsrc(in.PN2, stride4);
@@ -647,7 +681,11 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         if constexpr (PIPE) {
             const int kk = min(j + 2, H);
             k.na = buf_load(par, kk);
-            k.nn = buf_load(pnr, kk);
+            if constexpr (RT) {
+                k.nn = (int)buf_load(pnr, kk) * 2;
+            } else {
+                k.nn = buf_load(pnr, kk);
+            }
         }
         if constexpr (BLK) {
             k.ps = buf_load(psr, j + 1);              // past the table: 0, never used
@@ -690,15 +728,16 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
     float pkP[PIPE ? SW : 1];
     int fSP[PIPE ? SW : 1];
     if constexpr (PIPE) {
-        const float nA0 = readlane_f(eA[0], 0), nN0 = readlane_f(eN[0], 0);
+        const float nA0 = readlane_f(eA[0], 0);
+        const NT nN0 = readlane_n(eN[0], 0);
 #pragma unroll
         for (int t = 0; t < SW; ++t) {
             if constexpr (BAND) {
-                const uint32_t fr = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, bcm[t]);
+                const uint32_t fr = (uint32_t)mean_of(eA[t] - nA0, eN[t] - nN0, bcm[t]);
                 pkP[t] = po_at((fr << 8) + lane4b, bsb[t]);
                 fSP[t] = (int)(fr << 2) + bqo[t];
             } else {
-                const uint32_t fi = (uint32_t)mean_index(eA[t] - nA0, eN[t] - nN0, cmean);
+                const uint32_t fi = (uint32_t)mean_of(eA[t] - nA0, eN[t] - nN0, cmean);
                 pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
                 fSP[t] = (int)fi;
             }
@@ -733,7 +772,8 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
         // row j's object cost, mean and prefix values, read from its owning
         // lane; the slot is chosen by wave-uniform branches (an indexed
         // choice would put the slot registers in scratch memory)
-        float Co = 0.0f, bA = 0.0f, bN = 0.0f;
+        float Co = 0.0f, bA = 0.0f;
+        NT bN = 0;
         int fp = 0;
         auto read_row = [&]() {
 #pragma unroll
@@ -743,7 +783,7 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                     fp = readlane_i(fO[t], jl);
                     if constexpr (!PIPE) {
                         bA = readlane_f(eA[t], jl);
-                        bN = readlane_f(eN[t], jl);
+                        bN = readlane_n(eN[t], jl);
                     }
                 }
             }
@@ -758,14 +798,14 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                     bc[0] = Co;
                     bc[1] = __builtin_bit_cast(float, fp);
                     bc[2] = bA;
-                    bc[3] = bN;
+                    bc[3] = __builtin_bit_cast(float, bN);
                 }
             }
             __syncthreads();
             Co = bc[0];
             fp = __builtin_bit_cast(int, bc[1]);
             bA = bc[2];
-            bN = bc[3];
+            bN = __builtin_bit_cast(NT, bc[3]);
         }
         // the b-side object prefix column moves to PO[.][j+1]
 #pragma unroll
@@ -791,11 +831,11 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 const int s = t * W + wave;
                 if (s < sj) continue;
                 if constexpr (BAND) {
-                    const uint32_t fr = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, bcm[t]);
+                    const uint32_t fr = (uint32_t)mean_of(eA[t] - bA, eN[t] - bN, bcm[t]);
                     pk[t] = po_at((fr << 8) + lane4b, bsb[t]);
                     fS[t] = (int)(fr << 2) + bqo[t];
                 } else {
-                    const uint32_t fi = (uint32_t)mean_index(eA[t] - bA, eN[t] - bN, cmean);
+                    const uint32_t fi = (uint32_t)mean_of(eA[t] - bA, eN[t] - bN, cmean);
                     pk[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(s * 256));
                     fS[t] = (int)fi;
                 }
@@ -880,6 +920,19 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
             Xgo_d = Xgo + P.c_dive;
             Xgo_g = Xgo + P.c_grav;
         }
+        // RT: the reciprocals of the next step's candidates (row j+1's
+        // count), read before the table is written, so that their LDS
+        // latency passes under it instead of in front of each gather
+        float rP[(PIPE && RT) ? SW : 1];
+        if constexpr (PIPE && RT) {
+            const NT nN = readlane_n(blk.nn, jl);
+#pragma unroll
+            for (int t = 0; t < SW; ++t) {
+                if (t < sj) continue;
+                rP[t] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(rtab) +
+                                                        (eN[t] - nN));
+            }
+        }
         // this wave's copy of the table (LDS accesses of one wave complete
         // in order, so no barrier guards it)
 #pragma unroll
@@ -904,7 +957,8 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
             // fold the gathers issued a step ago, then issue the next
             // step's (base b+1: row j+1's prefix values); a slot that closes
             // with this step still gathers once, into rows never folded
-            const float nA = readlane_f(blk.na, jl), nN = readlane_f(blk.nn, jl);
+            const float nA = readlane_f(blk.na, jl);
+            const NT nN = readlane_n(blk.nn, jl);
             float qv[SW];
 #pragma unroll
             for (int t = 0; t < SW; ++t) {
@@ -927,11 +981,16 @@ __device__ __forceinline__ void solve_column(const int H, const int vtop, const 
                 fO[t] = better ? fSP[t] : fO[t];
                 if constexpr (LINKS) bO[t] = better ? b : bO[t];
                 if constexpr (BAND) {
-                    const uint32_t fr = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, bcm[t]);
+                    uint32_t fr;
+                    if constexpr (RT) {
+                        fr = (uint32_t)cvt_i32_nan0(__builtin_fmaf(eA[t] - nA, rP[t], bcm[t]));
+                    } else {
+                        fr = (uint32_t)mean_of(eA[t] - nA, eN[t] - nN, bcm[t]);
+                    }
                     pkP[t] = po_at((fr << 8) + lane4b, bsb[t]);
                     fSP[t] = (int)(fr << 2) + bqo[t];
                 } else {
-                    const uint32_t fi = (uint32_t)mean_index(eA[t] - nA, eN[t] - nN, cmean);
+                    const uint32_t fi = (uint32_t)mean_of(eA[t] - nA, eN[t] - nN, cmean);
                     pkP[t] = po_at(__umul24(fi, pstride4) + lane4, (uint32_t)(t * 256));
                     fSP[t] = (int)fi;
                 }
