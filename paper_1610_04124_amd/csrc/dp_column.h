@@ -52,7 +52,8 @@ struct ColumnIn {
     const int* band_base = nullptr;
     uint32_t po_bytes = 0;  // bytes of the PO table (0: its rows times po_stride)
     // solve_column with RT: rcp(2 n) for n = 0 .. 64 S (LDS), the values
-    // v_rcp_f32 gives, read in place of that quarter-rate instruction
+    // v_rcp_f32 gives, read in place of that instruction (which takes about
+    // two VALU issue slots)
     const float* rtab = nullptr;
     const int16_t* q;       // [H] reduced disparities of the column (LDS), -1 invalid
     const float* O_df;      // [D][D] object cost, row d (pixel disparity), column f (mean)
@@ -506,8 +507,8 @@ __device__ __forceinline__ void backtrack_links(const int H, const int vtop, con
 // of a candidate's rounded mean comes from in.rtab (an LDS table of the
 // values v_rcp_f32 gives, so every mean is the same), the row counts are
 // kept as byte offsets n * 4 into it: one LDS read replaces a subtraction
-// and a v_rcp_f32, which issues at a quarter of the VALU rate.  On return
-// the results are written.
+// and a v_rcp_f32, which takes about two VALU issue slots.  On return the
+// results are written.
 template <int S, int NCH, int W, bool POL = false, bool BLOCKS = true, bool LINKS = false,
           bool BAND = false, bool RT = false>
 __device__ __forceinline__ void solve_column(const int H, const int vtop, const Prior P, const ColumnIn& in,
