@@ -96,13 +96,16 @@ __device__ __forceinline__ int dpp_i(int old, int x) {
     return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
 }
 
-// Minimum over the 64 lanes: row minima by DPP row shifts (lanes whose
-// source lies outside the row keep kBig), then the four row results.
+// Minimum over the 64 lanes: row minima by DPP row shifts, then the four
+// row results.  Lanes whose source lies outside the row take INT_MAX, the
+// identity of the minimum, so that each shift and minimum is one
+// v_min_i32_dpp (another fill value costs a move per shift).
 __device__ __forceinline__ int wave_min(int x) {
-    x = min(x, dpp_i<0x111, 0xf>(kBig, x));   // row_shr:1
-    x = min(x, dpp_i<0x112, 0xf>(kBig, x));   // row_shr:2
-    x = min(x, dpp_i<0x114, 0xf>(kBig, x));   // row_shr:4
-    x = min(x, dpp_i<0x118, 0xf>(kBig, x));   // row_shr:8
+    constexpr int kId = 0x7fffffff;
+    x = min(x, dpp_i<0x111, 0xf>(kId, x));    // row_shr:1
+    x = min(x, dpp_i<0x112, 0xf>(kId, x));    // row_shr:2
+    x = min(x, dpp_i<0x114, 0xf>(kId, x));    // row_shr:4
+    x = min(x, dpp_i<0x118, 0xf>(kId, x));    // row_shr:8
     const int a = __builtin_amdgcn_readlane(x, 15), b = __builtin_amdgcn_readlane(x, 31);
     const int c = __builtin_amdgcn_readlane(x, 47), d = __builtin_amdgcn_readlane(x, 63);
     return min(min(a, b), min(c, d));
@@ -121,9 +124,13 @@ __device__ __forceinline__ int wave_min_key(int v) {
     return min(min(a, b), min(c, d));
 }
 
-// lane l receives lane l-1's x (lane 0 receives kBig), and lane l+1's
-__device__ __forceinline__ int from_below(int x) { return dpp_i<0x138, 0xf>(kBig, x); }  // wave_shr:1
-__device__ __forceinline__ int from_above(int x) { return dpp_i<0x130, 0xf>(kBig, x); }  // wave_shl:1
+// lane l receives lane l-1's x (lane 0 receives INT_MAX), and lane l+1's
+// (lane 63 INT_MAX).  The path step takes them only in a minimum with the
+// other neighbour, which is a path cost, so INT_MAX never survives to the
+// addition of P1; as the identity of the minimum it lets the shift fold into
+// a v_min_i32_dpp.
+__device__ __forceinline__ int from_below(int x) { return dpp_i<0x138, 0xf>(0x7fffffff, x); }  // wave_shr:1
+__device__ __forceinline__ int from_above(int x) { return dpp_i<0x130, 0xf>(0x7fffffff, x); }  // wave_shl:1
 
 __device__ __forceinline__ int popc64(uint64_t v) {
     return __builtin_popcount((uint32_t)v) + __builtin_popcount((uint32_t)(v >> 32));
