@@ -108,6 +108,59 @@ def shader_clock_mhz():
     return None
 
 
+def sclk_sysfs_path(index=0):
+    """sysfs file of the device's shader clock levels (the active one is
+    marked '*'), found by the device's PCI address, or None."""
+    import torch
+    p = torch.cuda.get_device_properties(index)
+    path = (f"/sys/bus/pci/devices/{p.pci_domain_id:04x}:{p.pci_bus_id:02x}:"
+            f"{p.pci_device_id:02x}.0/pp_dpm_sclk")
+    return path if os.path.exists(path) else None
+
+
+def read_sclk_mhz(path):
+    try:
+        for line in open(path):
+            if "*" in line:
+                return float(line.split(":", 1)[1].lower().split("mhz")[0])
+    except (OSError, ValueError, IndexError):
+        pass
+    return None
+
+
+class ClockSampler:
+    """Reads the active shader clock level from sysfs on a thread, every few
+    milliseconds, while a timed region runs (a file read: no process is
+    started).  median() is None where the file is not readable."""
+
+    def __init__(self, path, period_s=0.002):
+        self.path, self.period, self.samples = path, period_s, []
+
+    def __enter__(self):
+        import threading
+        self.stop = threading.Event()
+        self.thread = None
+        if self.path:
+            def run():
+                while not self.stop.is_set():
+                    v = read_sclk_mhz(self.path)
+                    if v is not None:
+                        self.samples.append(v)
+                    self.stop.wait(self.period)
+            self.thread = threading.Thread(target=run, daemon=True)
+            self.thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.set()
+        if self.thread:
+            self.thread.join()
+        return False
+
+    def median(self):
+        return statistics.median(self.samples) if self.samples else None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -637,7 +690,8 @@ def main():
     grid, ntasks = batch.info()
     waves = batch.waves()
     columns = batch.columns()
-    wall, launch_ms = time_replays(batch, stream, args.warmup, args.steps)
+    with ClockSampler(sclk_sysfs_path()) as clock:
+        wall, launch_ms = time_replays(batch, stream, args.warmup, args.steps)
     batched_fps = FRAMES * args.steps / wall
     ms_per_step = wall * 1e3 / args.steps
     avg_launch_s = statistics.mean(launch_ms) * 1e-3
@@ -655,7 +709,13 @@ def main():
                 "ops_per_launch": ops, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
                 "frac_7op": round(OPS_SEPARABLE * pairs / avg_launch_s / VALU_PEAK, 4),
                 "valu_busy_counters": valu_busy,
-                "sclk_mhz_at_start": sclk}
+                "sclk_mhz_at_start": sclk,
+                "sclk_mhz_during_timing": clock.median(),
+                "sclk_samples": len(clock.samples)}
+    if clock.median():
+        # the same fraction against the VALU rate at the clock observed while timing
+        roofline["frac_at_observed_sclk"] = round(
+            achieved / (VALU_PEAK * clock.median() / 2400.0), 4)
 
     # ---------------- per-frame paths
     per_frame = per_frame_legs(h, d_frames, outs, stream, args.steps, args.latency_frames,
