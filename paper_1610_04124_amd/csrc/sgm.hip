@@ -180,6 +180,14 @@ __device__ __forceinline__ void store_s(uint16_t* S, size_t e, const int (&v)[DP
 
 enum { kFirst = 0, kAdd = 1, kFinal = 2 };
 
+// A bijection of [0, n): block b, the (b / 8)-th block dispatched to XCD
+// b mod 8, becomes the (b / 8)-th of that XCD's contiguous range (XCD x
+// holds n / 8 blocks, one more if x < n mod 8).
+__device__ __forceinline__ int xcd_contiguous(int b, int n) {
+    const int x = b & 7, j = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + j;
+}
+
 
 // One path line per wave (a workgroup of one wave).  DIR: 0 left to right,
 // 1 right to left, 2 top to bottom, 3 bottom to top.  MODE: kFirst writes S,
@@ -192,7 +200,12 @@ __global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
     const int lane = threadIdx.x;
     const int W = a.W, H = a.H, D = a.D;
     const int lines = HORZ ? H : W;
-    const int f = blockIdx.x / lines, line = blockIdx.x - f * lines;
+    // Workgroups go to the eight XCDs in turn; the launch's blocks are
+    // renumbered so that each XCD takes a contiguous range of path lines:
+    // neighbouring columns read nearly the same right-view census words
+    // every step, and only on one XCD do they share its L2.
+    const int bid = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    const int f = bid / lines, line = bid - f * lines;
     const size_t fo = (size_t)f * (size_t)W * (size_t)H;
     const uint64_t* __restrict__ cl = a.cl + fo;
     const uint64_t* __restrict__ cr = a.cr + fo;
