@@ -192,20 +192,40 @@ __device__ __forceinline__ int xcd_contiguous(int b, int n) {
 // One path line per wave (a workgroup of one wave).  DIR: 0 left to right,
 // 1 right to left, 2 top to bottom, 3 bottom to top.  MODE: kFirst writes S,
 // kAdd adds to it, kFinal (left to right only) selects and checks.
-template <int DPL, int DIR, int MODE>
-__global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
+// LDS hand-off between the waves of a workgroup: this wave's LDS writes
+// have completed before the barrier, and its global loads in flight (later
+// steps' operands) are not waited for, as a full fence would.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);               // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// G waves per workgroup (G > 1: column passes only) take G neighbouring
+// path lines, one each, and share the right-view census words through LDS.
+template <int DPL, int DIR, int MODE, int G = 1>
+__global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
     static_assert(MODE != kFinal || DIR == 0, "the final pass runs left to right");
+    static_assert(G == 1 || DIR >= 2, "shared census words: column passes");
     extern __shared__ uint32_t lds[];                  // kFinal: keyR[W], then dL[W] (int16)
     constexpr bool HORZ = DIR <= 1;
-    const int lane = threadIdx.x;
+    constexpr bool STG = G > 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int W = a.W, H = a.H, D = a.D;
     const int lines = HORZ ? H : W;
+    const int groups = (lines + G - 1) / G;            // workgroups per frame
     // Workgroups go to the eight XCDs in turn; the launch's blocks are
     // renumbered so that each XCD takes a contiguous range of path lines:
     // neighbouring columns read nearly the same right-view census words
     // every step, and only on one XCD do they share its L2.
     const int bid = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
-    const int f = bid / lines, line = bid - f * lines;
+    const int f = bid / groups, grp = bid - f * groups;
+    // a wave past the last line (G not dividing the lines) repeats the last
+    // line with its stores off, so that it still takes part in the barriers
+    const bool line_ok = grp * G + wv < lines;
+    const int line = min(grp * G + wv, lines - 1);
     const size_t fo = (size_t)f * (size_t)W * (size_t)H;
     const uint64_t* __restrict__ cl = a.cl + fo;
     const uint64_t* __restrict__ cr = a.cr + fo;
@@ -249,7 +269,7 @@ __global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
     constexpr int kAhead = 4;
     uint64_t rcl[kAhead], rcr[kAhead][DPL];
     SWord<DPL> rsv[kAhead];
-    const bool live = d0 < D;
+    const bool live = d0 < D && line_ok;
     // element of S a step loads: lanes past the disparity range (whose
     // values are never used) load the pixel's last DPL entries
     const int d0l = min(d0, D - DPL);
@@ -261,8 +281,50 @@ __global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
 #pragma unroll
     for (int u = 0; u < kAhead; ++u) {
         const int sa = min(u, steps - 1);
-        load_ops(sa, rcl[u], rcr[u]);
+        if constexpr (STG) {
+            int y, x;
+            pixel(sa, y, x);
+            rcl[u] = cl[(size_t)y * W + x];
+        } else {
+            load_ops(sa, rcl[u], rcr[u]);
+        }
         if constexpr (MODE != kFirst) rsv[u] = load_s_word<DPL>(S, s_index(sa));
+    }
+    // STG: the right-view words of a group of kAhead rows for all G lines
+    // (word j of a row: column x0 - 64 DPL + 1 + j, clamped to the image),
+    // loaded by the whole workgroup a group ahead into registers, written to
+    // one of two LDS buffers at the group's start and read there by each
+    // lane (its words j = wv + 64 DPL - 1 - d)
+    constexpr int NSW = 64 * DPL + G - 1;
+    constexpr int NPT = STG ? (kAhead * NSW + 64 * G - 1) / (64 * G) : 1;
+    // (one word past the rows takes the stores of idle threads: no branch)
+    __shared__ uint64_t cst[STG ? 2 : 1][STG ? kAhead * NSW + 1 : 1];
+    uint64_t cpre[NPT];
+    const int x0 = grp * G;
+    auto stage_load = [&](int s0) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int idx = (int)threadIdx.x + k * 64 * G;
+            const int r = min(idx / NSW, kAhead - 1), j = idx - (idx / NSW) * NSW;
+            int y, x;
+            pixel(min(s0 + r, steps - 1), y, x);
+            cpre[k] = cr[(size_t)y * W + min(max(x0 - 64 * DPL + 1 + j, 0), W - 1)];
+        }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < NPT; ++k)
+            cst[buf][min((int)threadIdx.x + k * 64 * G, kAhead * NSW)] = cpre[k];
+    };
+    auto stage_ops = [&](int buf, int u, uint64_t (&crc)[DPL]) {
+#pragma unroll
+        for (int i = 0; i < DPL; ++i) crc[i] = cst[buf][u * NSW + wv + 64 * DPL - 1 - (d0 + i)];
+    };
+    if constexpr (STG) {
+        stage_load(0);
+        stage_store(0);
+        lds_barrier();
+        stage_load(kAhead);
     }
 
     int Lp[DPL];
@@ -336,24 +398,50 @@ __global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
     // unused: a branch here would make each ring slot a merge of two values)
     const int full = steps - steps % kAhead;
     for (int s0 = 0; s0 < full; s0 += kAhead) {
+        const int buf = (s0 / kAhead) & 1;
 #pragma unroll
         for (int u = 0; u < kAhead; ++u) {
             const int s = s0 + u;
             const uint64_t clc = rcl[u];
             uint64_t crc[DPL];
+            if constexpr (STG) {
+                stage_ops(buf, u, crc);
+            } else {
 #pragma unroll
-            for (int i = 0; i < DPL; ++i) crc[i] = rcr[u][i];
+                for (int i = 0; i < DPL; ++i) crc[i] = rcr[u][i];
+            }
             const SWord<DPL> sw = rsv[u];
             const int sa = min(s + kAhead, steps - 1);
-            load_ops(sa, rcl[u], rcr[u]);
+            if constexpr (STG) {
+                int y, x;
+                pixel(sa, y, x);
+                rcl[u] = cl[(size_t)y * W + x];
+            } else {
+                load_ops(sa, rcl[u], rcr[u]);
+            }
             if constexpr (MODE != kFirst) rsv[u] = load_s_word<DPL>(S, s_index(sa));
             step(s, clc, crc, sw);
+        }
+        if constexpr (STG) {
+            // the next group's words into the other buffer (whose last
+            // readers passed the previous barrier), then the group after
+            stage_store(buf ^ 1);
+            lds_barrier();
+            stage_load(s0 + 2 * kAhead);
         }
     }
     // the last steps % kAhead steps, already loaded
 #pragma unroll
     for (int u = 0; u < kAhead - 1; ++u) {
-        if (full + u < steps) step(full + u, rcl[u], rcr[u], rsv[u]);
+        if (full + u < steps) {
+            if constexpr (STG) {
+                uint64_t crc[DPL];
+                stage_ops((full / kAhead) & 1, u, crc);
+                step(full + u, rcl[u], crc, rsv[u]);
+            } else {
+                step(full + u, rcl[u], rcr[u], rsv[u]);
+            }
+        }
     }
     if constexpr (MODE == kFinal) {
         __syncthreads();
@@ -370,11 +458,20 @@ __global__ __launch_bounds__(64) void path_kernel(PathArgs a) {
     }
 }
 
+// columns per workgroup of the column passes (64 pairs 1024x440, 128
+// disparities: 16.7 ms per stage with one column per workgroup, 16.5 / 15.7 /
+// 15.3 / 15.0 ms with 2 / 4 / 8 / 16)
+constexpr int kColumnWaves = 16;
+
 template <int DPL>
 hipError_t launch_paths(const PathArgs& a, int frames, hipStream_t st) {
-    const unsigned rows = (unsigned)(frames * a.H), cols = (unsigned)(frames * a.W);
-    hipLaunchKernelGGL((path_kernel<DPL, 2, kFirst>), dim3(cols), dim3(64), 0, st, a);
-    hipLaunchKernelGGL((path_kernel<DPL, 3, kAdd>), dim3(cols), dim3(64), 0, st, a);
+    // the column passes take kColumnWaves columns per workgroup
+    const unsigned rows = (unsigned)(frames * a.H);
+    const unsigned cgroups = (unsigned)(frames * ((a.W + kColumnWaves - 1) / kColumnWaves));
+    hipLaunchKernelGGL((path_kernel<DPL, 2, kFirst, kColumnWaves>), dim3(cgroups),
+                       dim3(64 * kColumnWaves), 0, st, a);
+    hipLaunchKernelGGL((path_kernel<DPL, 3, kAdd, kColumnWaves>), dim3(cgroups),
+                       dim3(64 * kColumnWaves), 0, st, a);
     hipLaunchKernelGGL((path_kernel<DPL, 1, kAdd>), dim3(rows), dim3(64), 0, st, a);
     const size_t lds = (size_t)a.W * sizeof(uint32_t) + (size_t)a.W * sizeof(int16_t);
     hipLaunchKernelGGL((path_kernel<DPL, 0, kFinal>), dim3(rows), dim3(64), lds, st, a);
