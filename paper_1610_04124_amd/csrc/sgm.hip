@@ -211,6 +211,9 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
     extern __shared__ uint32_t lds[];                  // kFinal: keyR[W], then dL[W] (int16)
     constexpr bool HORZ = DIR <= 1;
     constexpr bool STG = G > 1;
+    // right to left: each step's right-view words are the previous step's
+    // moved by one disparity (SLIDE)
+    constexpr bool SLIDE = DIR == 1;
     const int lane = threadIdx.x & 63;
     const int wv = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int W = a.W, H = a.H, D = a.D;
@@ -267,7 +270,8 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
     // (4: 17.2 ms per 64 pairs of 1024x440, 128 disparities, against 20.7 ms
     // loading a step ahead; 8 steps ahead gained 1 % more for twice the ring)
     constexpr int kAhead = 4;
-    uint64_t rcl[kAhead], rcr[kAhead][DPL];
+    uint64_t rcl[kAhead], rcr[kAhead][DPL], rin[SLIDE ? kAhead : 1];
+    uint64_t win[DPL];
     SWord<DPL> rsv[kAhead];
     const bool live = d0 < D && line_ok;
     // element of S a step loads: lanes past the disparity range (whose
@@ -278,13 +282,35 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
         pixel(s, y, x);
         return ((size_t)y * W + x) * (size_t)D + (size_t)d0l;
     };
+    // SLIDE: the window of right-view words (lane l, word i: disparity
+    // DPL l + i) moves one lane up after each step (wave_shl:1) and takes in
+    // the word of the window's last disparity at lane 63, so that a step
+    // loads two uniform words instead of DPL per lane
+    auto entering = [&](int s) -> uint64_t {
+        int y, x;
+        pixel(s, y, x);
+        return cr[(size_t)y * W + max(x - (64 * DPL - 1), 0)];
+    };
+    auto slide = [&](uint64_t e) {
+        const uint64_t first = win[0];
+#pragma unroll
+        for (int i = 0; i < DPL - 1; ++i) win[i] = win[i + 1];
+        const int lo = dpp_i<0x130, 0xf>((int)(uint32_t)e, (int)(uint32_t)first);
+        const int hi = dpp_i<0x130, 0xf>((int)(uint32_t)(e >> 32), (int)(uint32_t)(first >> 32));
+        win[DPL - 1] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    };
+    if constexpr (SLIDE) {
+        uint64_t c0;
+        load_ops(0, c0, win);
+    }
 #pragma unroll
     for (int u = 0; u < kAhead; ++u) {
         const int sa = min(u, steps - 1);
-        if constexpr (STG) {
+        if constexpr (STG || SLIDE) {
             int y, x;
             pixel(sa, y, x);
             rcl[u] = cl[(size_t)y * W + x];
+            if constexpr (SLIDE) rin[u] = entering(sa);
         } else {
             load_ops(sa, rcl[u], rcr[u]);
         }
@@ -406,21 +432,28 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
             uint64_t crc[DPL];
             if constexpr (STG) {
                 stage_ops(buf, u, crc);
+            } else if constexpr (SLIDE) {
+#pragma unroll
+                for (int i = 0; i < DPL; ++i) crc[i] = win[i];
             } else {
 #pragma unroll
                 for (int i = 0; i < DPL; ++i) crc[i] = rcr[u][i];
             }
             const SWord<DPL> sw = rsv[u];
+            // SLIDE: the entering word of step s+1 (its slot is reloaded there)
+            const uint64_t en = rin[SLIDE ? (u + 1) % kAhead : 0];
             const int sa = min(s + kAhead, steps - 1);
-            if constexpr (STG) {
+            if constexpr (STG || SLIDE) {
                 int y, x;
                 pixel(sa, y, x);
                 rcl[u] = cl[(size_t)y * W + x];
+                if constexpr (SLIDE) rin[u] = entering(sa);
             } else {
                 load_ops(sa, rcl[u], rcr[u]);
             }
             if constexpr (MODE != kFirst) rsv[u] = load_s_word<DPL>(S, s_index(sa));
             step(s, clc, crc, sw);
+            if constexpr (SLIDE) slide(en);
         }
         if constexpr (STG) {
             // the next group's words into the other buffer (whose last
@@ -438,6 +471,9 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
                 uint64_t crc[DPL];
                 stage_ops((full / kAhead) & 1, u, crc);
                 step(full + u, rcl[u], crc, rsv[u]);
+            } else if constexpr (SLIDE) {
+                step(full + u, rcl[u], win, rsv[u]);
+                slide(rin[u + 1]);
             } else {
                 step(full + u, rcl[u], rcr[u], rsv[u]);
             }
