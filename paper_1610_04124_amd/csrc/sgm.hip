@@ -96,32 +96,23 @@ __device__ __forceinline__ int dpp_i(int old, int x) {
     return __builtin_amdgcn_update_dpp(old, x, CTRL, ROWMASK, 0xf, false);
 }
 
-// Minimum over the 64 lanes: row minima by DPP row shifts, then the four
-// row results.  Lanes whose source lies outside the row take INT_MAX, the
-// identity of the minimum, so that each shift and minimum is one
-// v_min_i32_dpp (another fill value costs a move per shift).
-__device__ __forceinline__ int wave_min(int x) {
-    constexpr int kId = 0x7fffffff;
-    x = min(x, dpp_i<0x111, 0xf>(kId, x));    // row_shr:1
-    x = min(x, dpp_i<0x112, 0xf>(kId, x));    // row_shr:2
-    x = min(x, dpp_i<0x114, 0xf>(kId, x));    // row_shr:4
-    x = min(x, dpp_i<0x118, 0xf>(kId, x));    // row_shr:8
-    const int a = __builtin_amdgcn_readlane(x, 15), b = __builtin_amdgcn_readlane(x, 31);
-    const int c = __builtin_amdgcn_readlane(x, 47), d = __builtin_amdgcn_readlane(x, 63);
-    return min(min(a, b), min(c, d));
-}
-
-// Minimum of non-negative keys over the 64 lanes (selection keys stay
-// below 2^23; lanes without a key hold kNoKey).
+// Minimum over the 64 lanes, in lane 63: row prefix minima by DPP row
+// shifts, then row 0's into row 1 and row 2's into row 3 (row_bcast:15),
+// then lane 31's into rows 2 and 3 (row_bcast:31).  Lanes without a source
+// take INT_MAX, the identity of the minimum, so that each shift and minimum
+// is one v_min_i32_dpp (another fill value costs a move per shift).
 constexpr int kNoKey = 0x7fffffff;
-__device__ __forceinline__ int wave_min_key(int v) {
-    v = min(v, dpp_i<0x111, 0xf>(kNoKey, v));
-    v = min(v, dpp_i<0x112, 0xf>(kNoKey, v));
-    v = min(v, dpp_i<0x114, 0xf>(kNoKey, v));
-    v = min(v, dpp_i<0x118, 0xf>(kNoKey, v));
-    const int a = __builtin_amdgcn_readlane(v, 15), b = __builtin_amdgcn_readlane(v, 31);
-    const int c = __builtin_amdgcn_readlane(v, 47), d = __builtin_amdgcn_readlane(v, 63);
-    return min(min(a, b), min(c, d));
+__device__ __forceinline__ int wave_min_in63(int x) {
+    x = min(x, dpp_i<0x111, 0xf>(kNoKey, x));    // row_shr:1
+    x = min(x, dpp_i<0x112, 0xf>(kNoKey, x));    // row_shr:2
+    x = min(x, dpp_i<0x114, 0xf>(kNoKey, x));    // row_shr:4
+    x = min(x, dpp_i<0x118, 0xf>(kNoKey, x));    // row_shr:8
+    x = min(x, dpp_i<0x142, 0xa>(kNoKey, x));    // row_bcast:15 into rows 1 and 3
+    x = min(x, dpp_i<0x143, 0xc>(kNoKey, x));    // row_bcast:31 into rows 2 and 3
+    return x;
+}
+__device__ __forceinline__ int wave_min(int x) {
+    return __builtin_amdgcn_readlane(wave_min_in63(x), 63);
 }
 
 // lane l receives lane l-1's x (lane 0 receives INT_MAX), and lane l+1's
@@ -415,8 +406,9 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
                     if (x - d >= 0) atomicMin(&keyR[x - d], (uint32_t)k);
                 }
             }
-            const int kmin = wave_min_key(key);
-            if (lane == 0) dLrow[x] = (int16_t)(kmin & 0xff);
+            // lanes without a key hold kNoKey; selection keys stay below 2^23
+            const int kmin = wave_min_in63(key);
+            if (lane == 63) dLrow[x] = (int16_t)(kmin & 0xff);
         }
     };
     // whole groups of kAhead steps, each step issuing the loads of the step
