@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "handle.h"
+#include "internal.h"
 #include "sgm.h"
 #include "stixels.h"
 
@@ -202,9 +203,12 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
     extern __shared__ uint32_t lds[];                  // kFinal: keyR[W], then dL[W] (int16)
     constexpr bool HORZ = DIR <= 1;
     constexpr bool STG = G > 1;
-    // right to left: each step's right-view words are the previous step's
-    // moved by one disparity (SLIDE)
-    constexpr bool SLIDE = DIR == 1;
+    // along a row each step's right-view words are the previous step's moved
+    // by one disparity (SLIDE); the final pass reads its wave-uniform words by
+    // buffer loads (VLOAD): scalar loads share their wait counter with the
+    // pass's LDS atomics, so every wait for one would wait for those too
+    constexpr bool SLIDE = HORZ;
+    constexpr bool VLOAD = MODE == kFinal;
     const int lane = threadIdx.x & 63;
     const int wv = (G == 1) ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int W = a.W, H = a.H, D = a.D;
@@ -277,18 +281,49 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
     // DPL l + i) moves one lane up after each step (wave_shl:1) and takes in
     // the word of the window's last disparity at lane 63, so that a step
     // loads two uniform words instead of DPL per lane
+    const auto clr = make_rsrc(cl, (uint32_t)((size_t)W * H * 8));
+    const auto crr = make_rsrc(cr, (uint32_t)((size_t)W * H * 8));
+    // word e of a census map through its buffer resource (two dwords)
+    auto word_v = [&](__amdgpu_buffer_rsrc_t r, int e) -> uint64_t {
+        const uint32_t lo = __builtin_bit_cast(uint32_t, buf_load_b(r, (uint32_t)e * 8u, 0u));
+        const uint32_t hi = __builtin_bit_cast(uint32_t, buf_load_b(r, (uint32_t)e * 8u + 4u, 0u));
+        return ((uint64_t)hi << 32) | lo;
+    };
+    auto left_word = [&](int s) -> uint64_t {
+        int y, x;
+        pixel(s, y, x);
+        if constexpr (VLOAD) return word_v(clr, y * W + x);
+        else return cl[(size_t)y * W + x];
+    };
+    // the word that enters the window for step s: disparity 0 moving right,
+    // the window's last disparity moving left (column 0 past the image's
+    // left edge, as in load_ops)
     auto entering = [&](int s) -> uint64_t {
         int y, x;
         pixel(s, y, x);
-        return cr[(size_t)y * W + max(x - (64 * DPL - 1), 0)];
+        const int xr = (DIR == 0) ? x : max(x - (64 * DPL - 1), 0);
+        if constexpr (VLOAD) return word_v(crr, y * W + xr);
+        else return cr[(size_t)y * W + xr];
     };
+    // the window of the next step, with its entering word e: moving right
+    // lane l takes lane l-1's last word (wave_shr:1) and lane 0 takes e;
+    // moving left lane l takes lane l+1's first word (wave_shl:1) and lane
+    // 63 takes e
     auto slide = [&](uint64_t e) {
-        const uint64_t first = win[0];
+        constexpr int C = DIR == 0 ? 0x138 : 0x130;
+        const uint64_t v = (DIR == 0) ? win[DPL - 1] : win[0];
+        const int lo = dpp_i<C, 0xf>((int)(uint32_t)e, (int)(uint32_t)v);
+        const int hi = dpp_i<C, 0xf>((int)(uint32_t)(e >> 32), (int)(uint32_t)(v >> 32));
+        const uint64_t in = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+        if constexpr (DIR == 0) {
 #pragma unroll
-        for (int i = 0; i < DPL - 1; ++i) win[i] = win[i + 1];
-        const int lo = dpp_i<0x130, 0xf>((int)(uint32_t)e, (int)(uint32_t)first);
-        const int hi = dpp_i<0x130, 0xf>((int)(uint32_t)(e >> 32), (int)(uint32_t)(first >> 32));
-        win[DPL - 1] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+            for (int i = DPL - 1; i > 0; --i) win[i] = win[i - 1];
+            win[0] = in;
+        } else {
+#pragma unroll
+            for (int i = 0; i < DPL - 1; ++i) win[i] = win[i + 1];
+            win[DPL - 1] = in;
+        }
     };
     if constexpr (SLIDE) {
         uint64_t c0;
@@ -297,11 +332,13 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
 #pragma unroll
     for (int u = 0; u < kAhead; ++u) {
         const int sa = min(u, steps - 1);
-        if constexpr (STG || SLIDE) {
+        if constexpr (SLIDE) {
+            rcl[u] = left_word(sa);
+            rin[u] = entering(sa);
+        } else if constexpr (STG) {
             int y, x;
             pixel(sa, y, x);
             rcl[u] = cl[(size_t)y * W + x];
-            if constexpr (SLIDE) rin[u] = entering(sa);
         } else {
             load_ops(sa, rcl[u], rcr[u]);
         }
@@ -435,11 +472,13 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
             // SLIDE: the entering word of step s+1 (its slot is reloaded there)
             const uint64_t en = rin[SLIDE ? (u + 1) % kAhead : 0];
             const int sa = min(s + kAhead, steps - 1);
-            if constexpr (STG || SLIDE) {
+            if constexpr (SLIDE) {
+                rcl[u] = left_word(sa);
+                rin[u] = entering(sa);
+            } else if constexpr (STG) {
                 int y, x;
                 pixel(sa, y, x);
                 rcl[u] = cl[(size_t)y * W + x];
-                if constexpr (SLIDE) rin[u] = entering(sa);
             } else {
                 load_ops(sa, rcl[u], rcr[u]);
             }
