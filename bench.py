@@ -314,6 +314,7 @@ def uneven(warmup, steps, tune_launch=True):
            "sizes": "640x240, 1024x440, 1280x720, 2048x880; stixel widths 3/5/7; one launch"}
     if tuned is not None:
         res["autotune_tried_ms"] = tuned["tried"]
+        res["autotune_refined_ms"] = tuned.get("refined")
     return res
 
 
@@ -741,6 +742,7 @@ def main():
     }
     if tuned is not None:
         result["config"]["autotune_tried_ms"] = tuned["tried"]
+        result["config"]["autotune_refined_ms"] = tuned.get("refined")
     print("[bench] batched and per-frame legs done", file=sys.stderr, flush=True)
     result["hires_2048x880"] = hires(args.warmup, max(3, args.steps // 5), tune_launch)
     result["batched_mean_reduction"] = mean_mode(d_frames, args.warmup, max(3, args.steps // 5),
