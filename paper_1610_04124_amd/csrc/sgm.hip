@@ -278,9 +278,9 @@ __global__ __launch_bounds__(64 * G) void path_kernel(PathArgs a) {
         return ((size_t)y * W + x) * (size_t)D + (size_t)d0l;
     };
     // SLIDE: the window of right-view words (lane l, word i: disparity
-    // DPL l + i) moves one lane up after each step (wave_shl:1) and takes in
-    // the word of the window's last disparity at lane 63, so that a step
-    // loads two uniform words instead of DPL per lane
+    // DPL l + i) moves by one lane after each step and takes in one word at
+    // its edge lane, so that a step loads two wave-uniform words (the left
+    // view's and the entering one) instead of DPL per lane
     const auto clr = make_rsrc(cl, (uint32_t)((size_t)W * H * 8));
     const auto crr = make_rsrc(cr, (uint32_t)((size_t)W * H * 8));
     // word e of a census map through its buffer resource (two dwords)
