@@ -159,55 +159,75 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
         }
     }
 
-    // Object rows: every load of a row (one per 64-row slot) is issued
-    // before its scan starts, so a row costs one memory latency rather than
-    // one per slot.  Each slot's pixel becomes a byte offset within an
-    // object-cost row once (2^30 for an invalid pixel or a row past H: in the
-    // per-lane offset, which the bounds check always covers, so such lanes
-    // read 0); a row's offset is the scalar part of every load, and the
-    // slots' scans carry no branch between them.
+    // Object rows f = fmin + wave, fmin + wave + 8, ...: row f of the object
+    // cost table (the cost of mean f for every pixel bin) is staged in this
+    // wave's LDS by a few coalesced loads (the next row's in flight while a
+    // row is scanned; a zero after it for invalid pixels and rows past H);
+    // lane l takes the costs of rows 256 u + 4 l .. 256 u + 4 l + 3 from the
+    // stage, sums them in order and adds the wave scan of the lanes' sums: one
+    // scan per 256 rows instead of one per 64, two cost loads per row instead
+    // of a gather per 64 rows.  Every cost is on the grid, so the prefixes are
+    // the same bits in any order of summation.
+    __shared__ float ostg[8][256 + 4];
     float* PO = a.po + (size_t)col * D * stride;
     const auto otr = make_rsrc(a.object_t, (uint32_t)(D * D) * 4u);
     const auto pow_ = make_rsrc(PO, (uint32_t)(fmax - fmin + 1) * (uint32_t)stride * 4u);
-    constexpr int kSlots = kMaxHeight / 64;
-    const int nsl = (H + 63) >> 6;
-    uint32_t qoff[kSlots];
+    constexpr int U = kMaxHeight / 256;          // 256-row groups
+    constexpr int NC = 4;                        // 64-bin chunks of a cost row (<= 256 bins)
+    const int nu = (H + 255) >> 8, nch = (D + 63) >> 6;
+    float* const stg = ostg[wave];
+    if (lane == 0) stg[D] = 0.0f;
+    int qi[U][4];                                // stage index of each row's cost
 #pragma unroll
-    for (int c = 0; c < kSlots; ++c) {
-        const int v = 64 * c + lane;
-        const int x = (v < H) ? (int)qs[v] : -1;
-        qoff[c] = (x >= 0) ? (uint32_t)x * 4u : 0x40000000u;
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = 256 * u + 4 * lane + i;
+            const int x = (v < H) ? (int)qs[v] : -1;
+            qi[u][i] = (x >= 0) ? x : D;
+        }
     }
-    const int f0 = __builtin_amdgcn_readfirstlane(fmin), f1 = __builtin_amdgcn_readfirstlane(fmax);
-#pragma unroll 1
-    for (int f = f0 + wave; f <= f1; f += 8) {
-        const uint32_t rowb = (uint32_t)(f * D) * 4u;
-        float oc[kSlots];
-        if (a.online) {
+    float onext[NC];
+    auto load_row = [&](int f) {
 #pragma unroll
-            for (int c = 0; c < kSlots; ++c) {
-                if (c >= nsl) break;
-                const int v = 64 * c + lane;
-                const int x = (v < H) ? (int)qs[v] : -1;
-                oc[c] = (x >= 0) ? object_cost_online(a, x, f) : 0.0f;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kSlots; ++c) {
-                if (c >= nsl) break;
-                oc[c] = buf_load_b(otr, qoff[c], rowb);
+        for (int c = 0; c < NC; ++c) {
+            if (c >= nch) break;
+            const int d = 64 * c + lane;
+            if (a.online) {
+                onext[c] = (d < D) ? object_cost_online(a, d, f) : 0.0f;
+            } else {
+                onext[c] = buf_load_b(otr, (uint32_t)d * 4u, (uint32_t)(f * D) * 4u);
             }
         }
+    };
+    const int f0 = __builtin_amdgcn_readfirstlane(fmin), f1 = __builtin_amdgcn_readfirstlane(fmax);
+    if (f0 + wave <= f1) load_row(f0 + wave);
+#pragma unroll 1
+    for (int f = f0 + wave; f <= f1; f += 8) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= nch) break;
+            if (64 * c + lane < D) stg[64 * c + lane] = onext[c];
+        }
+        if (f + 8 <= f1) load_row(f + 8);
         const uint32_t rowoff = (uint32_t)(f - f0) * (uint32_t)stride * 4u;
         if (lane == 0) buf_store_b(pow_, 0.0f, 0u, rowoff);
         float carry = 0.0f;
 #pragma unroll
-        for (int c = 0; c < kSlots; ++c) {
-            if (c >= nsl) break;
-            const int v = 64 * c + lane;
-            const float o = wave_inclusive_scan(oc[c]) + carry;
-            if (v < H) buf_store_b(pow_, o, (uint32_t)(v + 1) * 4u, rowoff);
-            carry = readlane_f(o, 63);
+        for (int u = 0; u < U; ++u) {
+            if (u >= nu) break;
+            const float o0 = stg[qi[u][0]], o1 = stg[qi[u][1]];
+            const float o2 = stg[qi[u][2]], o3 = stg[qi[u][3]];
+            const float a1 = o0 + o1, a2 = a1 + o2, a3 = a2 + o3;
+            const float incl = wave_inclusive_scan(a3);
+            const float e = (incl - a3) + carry;
+            const float r[4] = {e + o0, e + a1, e + a2, e + a3};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int v = 256 * u + 4 * lane + i;
+                if (v < H) buf_store_b(pow_, r[i], (uint32_t)(v + 1) * 4u, rowoff);
+            }
+            carry = readlane_f(incl, 63) + carry;
         }
     }
 }
