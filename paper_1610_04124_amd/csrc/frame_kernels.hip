@@ -118,44 +118,31 @@ __global__ __launch_bounds__(512) void tables_kernel(TablesArgs a) {
     }
     const int stride = H + 1;
 
-    if (wave == 0) {
-        float* PG = a.prefix + ((size_t)0 * ncols + col) * stride;
-        float* PS = a.prefix + ((size_t)1 * ncols + col) * stride;
-        float* PA = a.prefix + ((size_t)2 * ncols + col) * stride;
-        float* PN = a.prefix + ((size_t)3 * ncols + col) * stride;
+    if (wave < 4) {
+        // wave t scans small table t: ground, sky, 2q+1 and 2 over the valid
+        // pixels (four chains side by side rather than one after another)
+        const int t = __builtin_amdgcn_readfirstlane(wave);
+        float* P = a.prefix + ((size_t)t * ncols + col) * stride;
         if (lane == 0) {
-            PG[0] = 0.0f;
-            PS[0] = 0.0f;
-            PA[0] = 0.0f;
-            PN[0] = 0.0f;
-            a.range[2 * col] = fmin;
-            a.range[2 * col + 1] = fmax;
+            P[0] = 0.0f;
+            if (t == 0) {
+                a.range[2 * col] = fmin;
+                a.range[2 * col + 1] = fmax;
+            }
         }
-        float cg = 0.0f, cs = 0.0f, ca = 0.0f, cn = 0.0f;
+        float carry = 0.0f;
         for (int base = 0; base < H; base += 64) {
             const int v = base + lane;
             const int x = (v < H) ? (int)qs[v] : -1;
-            float g = 0.0f, sk = 0.0f, aa = 0.0f, nn = 0.0f;
+            float e = 0.0f;
             if (x >= 0) {
-                g = a.ground[(size_t)(H - 1 - v) * D + x];
-                sk = a.sky[x];
-                aa = (float)(2 * x + 1);
-                nn = 2.0f;
+                e = (t == 0) ? a.ground[(size_t)(H - 1 - v) * D + x]
+                  : (t == 1) ? a.sky[x]
+                  : (t == 2) ? (float)(2 * x + 1) : 2.0f;
             }
-            g = wave_inclusive_scan(g) + cg;
-            sk = wave_inclusive_scan(sk) + cs;
-            aa = wave_inclusive_scan(aa) + ca;
-            nn = wave_inclusive_scan(nn) + cn;
-            if (v < H) {
-                PG[v + 1] = g;
-                PS[v + 1] = sk;
-                PA[v + 1] = aa;
-                PN[v + 1] = nn;
-            }
-            cg = readlane_f(g, 63);
-            cs = readlane_f(sk, 63);
-            ca = readlane_f(aa, 63);
-            cn = readlane_f(nn, 63);
+            e = wave_inclusive_scan(e) + carry;
+            if (v < H) P[v + 1] = e;
+            carry = readlane_f(e, 63);
         }
     }
 
