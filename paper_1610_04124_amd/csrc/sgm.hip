@@ -68,12 +68,32 @@ __global__ __launch_bounds__(256) void census_kernel(const uint8_t* __restrict__
         tile[ty][tx] = (y >= 0 && y < H && x >= 0 && x < W) ? img[(size_t)y * W + x] : 256;
     }
     __syncthreads();
+    // thread (tx, g) takes the kTileH / 4 consecutive rows of group g in
+    // column tx, keeping the 7 x 9 window in registers and reading one new
+    // tile row per pixel (9 LDS reads instead of 63)
+    constexpr int kRows = kTileH / 4;
     const int tx = threadIdx.x & 63;
     const int x = x0 + tx;
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
+    const int r0 = (threadIdx.x >> 6) * kRows;
+    int win[7][9];
+#pragma unroll
+    for (int dy = 0; dy < 6; ++dy) {
+#pragma unroll
+        for (int dx = 0; dx < 9; ++dx) win[dy + 1][dx] = tile[r0 + dy][tx + dx];
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        const int r = r0 + k;
+#pragma unroll
+        for (int dy = 0; dy < 6; ++dy) {
+#pragma unroll
+            for (int dx = 0; dx < 9; ++dx) win[dy][dx] = win[dy + 1][dx];
+        }
+#pragma unroll
+        for (int dx = 0; dx < 9; ++dx) win[6][dx] = tile[r + 6][tx + dx];
         const int y = y0 + r;
         if (y >= H || x >= W) continue;
-        const int c = tile[r + 3][tx + 4];
+        const int c = win[3][4];
         uint32_t lo = 0u, hi = 0u;
         int b = 0;
 #pragma unroll
@@ -81,7 +101,7 @@ __global__ __launch_bounds__(256) void census_kernel(const uint8_t* __restrict__
 #pragma unroll
             for (int dx = 0; dx < 9; ++dx) {
                 if (dy == 3 && dx == 4) continue;
-                const uint32_t bit = tile[r + dy][tx + dx] < c ? 1u : 0u;
+                const uint32_t bit = win[dy][dx] < c ? 1u : 0u;
                 if (b < 32) lo |= bit << b;
                 else hi |= bit << (b - 32);
                 ++b;
