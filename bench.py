@@ -17,7 +17,8 @@ object mean, adds and minima), h(h+1)/2 pairs per column, against the plain
 VALU issue peak of 256 CUs x 64 lanes x 2.4 GHz = 39.32 T lane-ops/s (the
 recurrence is min-plus, not a contraction, so MFMA peaks do not apply).  The
 fraction by the 7 lane-ops the object candidate alone needs (the ground and
-sky minima are separable) is reported beside it.
+sky minima are separable) is reported beside it, and the fraction at the
+shader clock read from sysfs while the replays are timed.
 
     python bench.py [--steps K] [--warmup W]          the JSON line
     python bench.py --profile-mode MODE [--launches N] one workload for rocprofv3

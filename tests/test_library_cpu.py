@@ -220,3 +220,17 @@ def test_host_tables_off_the_grid_equal_oracle_in_fp32():
     assert np.array_equal(P.host_table(p, B.TABLE_FG_HI)[::-1], t["fg_hi"][:H])
     # some table value really is off the 2^-10 grid
     assert np.any(np.ldexp(t["S"], 10) != np.rint(np.ldexp(t["S"], 10)))
+
+
+def test_bench_reads_the_active_shader_clock_level(tmp_path):
+    """The bench's clock sampler parses the DPM level marked active."""
+    import bench
+    f = tmp_path / "pp_dpm_sclk"
+    f.write_text("0: 500Mhz\n1: 1600Mhz\n2: 2400Mhz *\n")
+    assert bench.read_sclk_mhz(str(f)) == 2400.0
+    f.write_text("0: 500Mhz\n1: 1600Mhz\n")
+    assert bench.read_sclk_mhz(str(f)) is None
+    assert bench.read_sclk_mhz(str(tmp_path / "missing")) is None
+    with bench.ClockSampler(None) as c:
+        pass
+    assert c.median() is None
